@@ -1,0 +1,308 @@
+"""Reference GADI iteration (oracle).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Algorithm 1 of Section 2.3 (mixed-precision GADI), run step by step:
+
+    x^(0) = 0
+    repeat
+        r^(k) = b - A x^(k)                              (u_r = FP64)
+        solve (alpha I + M) z^(k) = r^(k)                (u_s)
+        solve (alpha I + N) y^(k) = (2 - omega) alpha z^(k)   (u_s)
+        x^(k+1) = x^(k) + y^(k)                          (u = FP64)
+    until convergence
+
+Inner solvers (Section 5.1): conjugate gradients on H = alpha I + M, and CG
+on the normal equations for S = alpha I + N.  The normal-equation variant is
+read as Craig's method (CGNE), whose recursive residual is the residual of
+S y = c itself.  Both start from a zero guess and stop on the relative
+residual ||r_j|| <= tol ||r_0||, at a cap, or on stagnation (Section 5.1,
+early stop for BF16).
+
+Inner precision u_s is emulated: "f64" uses float64, "f32" float32 storage
+and arithmetic, "bf16" BF16 storage (round-to-nearest-even after every
+vector update) with float32 arithmetic; the operator coefficients are held in
+the arithmetic format (float32 for f32 and bf16).
+
+Stopping and status rules of the outer loop (readings):
+at the top of sweep k the residual of x^(k) is formed and
+    BE_k = ||r|| / (||A|| ||x^(k)|| + ||b||)           (backward error, Section 3)
+    relres_k = ||r|| / ||r^(0)||                        (the paper's Section 5 test)
+The iteration returns x^(k) with status
+    OK            when the chosen criterion <= tol,
+    DIVERGED      when BE_k is not finite or exceeds div_factor * min_j BE_j,
+    STAGNATED     when BE has not dropped below 0.99 of its last reference
+                  value for stag_window sweeps,
+    NOT_CONVERGED when k == max_outer,
+checked in that order.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import lowprec
+from .problems import hss_split, shifted
+
+OK, NOT_CONVERGED, STAGNATED, DIVERGED = 0, 1, 2, 3
+STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED",
+                DIVERGED: "DIVERGED"}
+
+# ||r_j|| must fall below 0.99 * (best so far) to count as progress: in
+# squared norms that is a factor 0.99**2.
+PROGRESS_SQ = 0.9801
+PROGRESS = 0.99
+
+
+@dataclasses.dataclass
+class InnerRule:
+    """Stopping rule of one inner solve (Section 5.1)."""
+    tol: float = 1e-3          # relative residual tolerance
+    max_iter: int = 2000       # cap on iterations
+    fixed: int = 0             # > 0: run exactly this many iterations, ignore the rest
+    stag_window: int = 20      # early stop: no 1% progress in this many iterations (0: off)
+
+    def stop(self, it: int, rho_new: float, rho0: float, tracker) -> bool:
+        """Decide after iteration ``it`` (1-based) with squared residual norm rho_new."""
+        if self.fixed > 0:
+            return it >= self.fixed
+        if not np.isfinite(rho_new):
+            return True
+        if rho_new <= (self.tol * self.tol) * rho0:
+            return True
+        if it >= self.max_iter:
+            return True
+        if rho_new < PROGRESS_SQ * tracker[0]:
+            tracker[0] = rho_new
+            tracker[1] = it
+        if self.stag_window > 0 and it - tracker[1] >= self.stag_window:
+            return True
+        return False
+
+
+def _rdot(a, b) -> float:
+    """Real part of a^H b in the arithmetic precision of the inputs."""
+    return np.real(np.vdot(a, b))
+
+
+def cg(H, c, rule: InnerRule, prec: str = "f64"):
+    """Conjugate gradients on the Hermitian positive definite H, zero initial guess.
+
+    Returns (z, iterations).  Each iteration: q = H p; a = rho / (p, q);
+    z += a p; r -= a q; rho' = (r, r); beta = rho'/rho; p = r + beta p.
+    """
+    cplx = np.iscomplexobj(c) or np.iscomplexobj(H.data)
+    dt = lowprec.arith_dtype(prec, cplx)
+    rt = np.float64 if prec == "f64" else np.float32
+    Hs = sp.csr_matrix(H, dtype=dt)
+    r = lowprec.store(np.asarray(c, dtype=dt), prec)
+    z = np.zeros_like(r)
+    rho0 = rt(_rdot(r, r))
+    if rho0 == 0:
+        return z, 0
+    p = r.copy()
+    rho = rho0
+    tracker = [float(rho0), 0]
+    it = 0
+    with np.errstate(all="ignore"):
+        while True:
+            q = Hs @ p
+            a = rt(rho / rt(_rdot(p, q)))
+            z = lowprec.store(z + a * p, prec)
+            r = lowprec.store(r - a * q, prec)
+            rho_new = rt(_rdot(r, r))
+            it += 1
+            if rule.stop(it, float(rho_new), float(rho0), tracker):
+                return z, it
+            beta = rt(rho_new / rho)
+            p = lowprec.store(r + beta * p, prec)
+            rho = rho_new
+
+
+def cgne(S, c, rule: InnerRule, prec: str = "f64"):
+    """Craig's method (CG on S S^H w = c, y = S^H w), zero initial guess.
+
+    Returns (y, iterations).  Each iteration: a = rho / (p, p); y += a p;
+    r -= a S p; rho' = (r, r); beta = rho'/rho; p = S^H r + beta p, with
+    p_0 = S^H c.  The recursive residual r_j is the residual c - S y_j.
+    """
+    cplx = np.iscomplexobj(c) or np.iscomplexobj(S.data)
+    dt = lowprec.arith_dtype(prec, cplx)
+    rt = np.float64 if prec == "f64" else np.float32
+    Ss = sp.csr_matrix(S, dtype=dt)
+    SHs = sp.csr_matrix(S.conj().T, dtype=dt)
+    r = lowprec.store(np.asarray(c, dtype=dt), prec)
+    y = np.zeros_like(r)
+    rho0 = rt(_rdot(r, r))
+    if rho0 == 0:
+        return y, 0
+    p = lowprec.store(SHs @ r, prec)
+    rho = rho0
+    tracker = [float(rho0), 0]
+    it = 0
+    with np.errstate(all="ignore"):
+        while True:
+            a = rt(rho / rt(_rdot(p, p)))
+            y = lowprec.store(y + a * p, prec)
+            r = lowprec.store(r - a * (Ss @ p), prec)
+            rho_new = rt(_rdot(r, r))
+            it += 1
+            if rule.stop(it, float(rho_new), float(rho0), tracker):
+                return y, it
+            beta = rt(rho_new / rho)
+            p = lowprec.store(SHs @ r + beta * p, prec)
+            rho = rho_new
+
+
+def backward_error(A, x, b, normA: float, extended: bool = False) -> float:
+    """Normwise backward error ||b - A x|| / (||A|| ||x|| + ||b||), 2-norms (Section 3).
+
+    With extended=True the residual is accumulated in np.longdouble.
+    """
+    if extended:
+        cplx = np.iscomplexobj(A.data) or np.iscomplexobj(x) or np.iscomplexobj(b)
+        dt = np.clongdouble if cplx else np.longdouble
+        xl = np.asarray(x, dtype=dt)
+        bl = np.asarray(b, dtype=dt)
+        r = bl - sp.csr_matrix(A).astype(dt) @ xl
+        nr = np.sqrt(np.sum(np.abs(r) ** 2))
+        nx = np.sqrt(np.sum(np.abs(xl) ** 2))
+        nb = np.sqrt(np.sum(np.abs(bl) ** 2))
+        return float(nr / (np.longdouble(normA) * nx + nb))
+    r = b - A @ x
+    return float(np.linalg.norm(r) / (normA * np.linalg.norm(x) + np.linalg.norm(b)))
+
+
+def forward_error(x, x_ref) -> float:
+    """||x - x_ref|| / ||x_ref|| (Section 3)."""
+    return float(np.linalg.norm(np.asarray(x) - np.asarray(x_ref)) / np.linalg.norm(x_ref))
+
+
+def norm2(A) -> float:
+    """||A||_2: dense SVD for small A, else the largest singular value from ARPACK."""
+    n = A.shape[0]
+    if n <= 1024:
+        return float(np.linalg.norm(A.toarray(), 2))
+    s = spla.svds(sp.csr_matrix(A), k=1, return_singular_vectors=False, tol=1e-14)
+    return float(s[0])
+
+
+@dataclasses.dataclass
+class GadiResult:
+    x: np.ndarray
+    status: int
+    outer: int
+    be: List[float]
+    relres: List[float]
+    inner_h: List[int]
+    inner_s: List[int]
+    iterates: Optional[List[np.ndarray]] = None
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES[self.status]
+
+
+def gadi(A, b, alpha: float, omega: float, *, normA: float, tol: float = 1e-10,
+         stop: str = "be", max_outer: int = 10000, inner: str = "mirror",
+         prec: str = "f64", rule_h: Optional[InnerRule] = None,
+         rule_s: Optional[InnerRule] = None, x0=None, stag_window: int = 200,
+         div_factor: float = 1e3, record_iterates: bool = False) -> GadiResult:
+    """Run Algorithm 1 (Section 2.3) on A x = b with the HSS splitting.
+
+    inner = "mirror": CG on H and Craig CGNE on S in precision ``prec``.
+    inner = "exact":  direct sparse LU solves of H and S (float64/complex128).
+    """
+    if not alpha > 0:
+        raise ValueError("alpha must be > 0")
+    if not 0.0 <= omega < 2.0:
+        raise ValueError("omega must lie in [0, 2)")
+    rule_h = rule_h or InnerRule()
+    rule_s = rule_s or InnerRule()
+    A = sp.csr_matrix(A)
+    cplx = np.iscomplexobj(A.data) or np.iscomplexobj(b)
+    wt = np.complex128 if cplx else np.float64
+    b = np.asarray(b, dtype=wt)
+    M, N = hss_split(A)
+    H, S = shifted(M, N, alpha)
+    gamma = (2.0 - omega) * alpha
+    if inner == "exact":
+        luH = spla.splu(sp.csc_matrix(H, dtype=wt))
+        luS = spla.splu(sp.csc_matrix(S, dtype=wt))
+    x = np.zeros(A.shape[0], dtype=wt) if x0 is None else np.array(x0, dtype=wt)
+    normb = float(np.linalg.norm(b))
+    res = GadiResult(x, OK, 0, [], [], [], [], [] if record_iterates else None)
+    be_best = np.inf
+    be_ref, k_ref = np.inf, 0
+    nr0 = None
+    k = 0
+    with np.errstate(all="ignore"):
+        while True:
+            if record_iterates:
+                res.iterates.append(x.copy())
+            r = b - A @ x                                    # residual in u_r = FP64
+            nr = float(np.linalg.norm(r))
+            be = nr / (normA * float(np.linalg.norm(x)) + normb)
+            if nr0 is None:
+                nr0 = nr
+            relres = nr / nr0 if nr0 > 0 else 0.0
+            res.be.append(be)
+            res.relres.append(relres)
+            crit = be if stop == "be" else relres
+            if crit <= tol:
+                res.status = OK
+                break
+            if not np.isfinite(be) or (div_factor > 0 and be > div_factor * be_best):
+                res.status = DIVERGED
+                break
+            be_best = min(be_best, be)
+            if k == 0 or be < PROGRESS * be_ref:
+                be_ref, k_ref = be, k
+            if stag_window > 0 and k - k_ref >= stag_window:
+                res.status = STAGNATED
+                break
+            if k >= max_outer:
+                res.status = NOT_CONVERGED
+                break
+            if inner == "exact":
+                z = luH.solve(r)
+                y = luS.solve(gamma * z)
+                jh = js = 1
+            else:
+                rs = lowprec.store(r.astype(lowprec.arith_dtype(prec, cplx)), prec)  # cast to u_s
+                z, jh = cg(H, rs, rule_h, prec)
+                c = lowprec.store(gamma * z, prec)
+                y, js = cgne(S, c, rule_s, prec)
+            res.inner_h.append(jh)
+            res.inner_s.append(js)
+            x = x + np.asarray(y, dtype=wt)                  # update in u = FP64
+            k += 1
+    res.x = x
+    res.outer = k
+    return res
+
+
+def gadi_two_step(A, b, alpha: float, omega: float, sweeps: int, x0=None):
+    """The two-step GADI form of Section 2.1 with exact solves, ``sweeps`` times.
+
+    (alpha I + M) x^(k+1/2) = (alpha I - N) x^(k) + b
+    (alpha I + N) x^(k+1)   = (N - (1 - omega) alpha I) x^(k) + (2 - omega) alpha x^(k+1/2)
+    Returns the list of iterates x^(0..sweeps).
+    """
+    A = sp.csr_matrix(A)
+    wt = np.complex128 if np.iscomplexobj(A.data) or np.iscomplexobj(b) else np.float64
+    M, N = hss_split(A)
+    I = sp.identity(A.shape[0], format="csr")
+    luH = spla.splu(sp.csc_matrix(alpha * I + M, dtype=wt))
+    luS = spla.splu(sp.csc_matrix(alpha * I + N, dtype=wt))
+    x = np.zeros(A.shape[0], dtype=wt) if x0 is None else np.array(x0, dtype=wt)
+    out = [x.copy()]
+    for _ in range(sweeps):
+        xh = luH.solve((alpha * I - N) @ x + b)
+        x = luS.solve((N - (1.0 - omega) * alpha * I) @ x + (2.0 - omega) * alpha * xh)
+        out.append(x.copy())
+    return out
