@@ -1,0 +1,236 @@
+/*
+ * gadi.h -- C ABI of the MI355X (gfx950) implementation of mixed-precision
+ * GADI (general alternating-direction implicit iteration) for A x = b.
+ *
+ * Method (arXiv 2512.21164):
+ *   splitting   A = M + N, H = alpha I + M, S = alpha I + N       eq. (split), Section 3.1
+ *               with the Hermitian / skew-Hermitian choice
+ *               M = (A + A^H)/2, N = (A - A^H)/2                  Sections 5.2-5.4
+ *   iteration   Algorithm 1 (Section 2.3): from x^(0),
+ *                 r = b - A x           in u_r  (FP64 here)
+ *                 solve H z = r         in u_s  (CG, Section 5.1)
+ *                 solve S y = (2-omega) alpha z   in u_s  (CG on the normal equations)
+ *                 x = x + y             in u    (FP64 here)
+ *   stopping    backward error ||b - A x|| / (||A|| ||x|| + ||b||) <= tol
+ *               (Section 3, 2-norms), or the relative residual ||r||/||r0||
+ *               that the experiments of Section 5 use.
+ *
+ * The operator A is matrix-free: a 5-point (2D) or 7-point (3D) constant
+ * coefficient stencil on the interior of a grid with zero Dirichlet values
+ * outside it (gadi_stencil).  Complex problems (Section 5.4) add a constant
+ * imaginary diagonal shift: A = L + i*shift_im*I.
+ *
+ * Memory.  The library never allocates device memory.  Every buffer is owned
+ * by the caller: the workspace (size from gadi_workspace_bytes), b and x.
+ * Device pointers are plain device addresses (e.g. torch tensor data_ptr()).
+ * Vectors are dense, x-fastest: index = i + nx*(j + ny*k).  Real problems use
+ * float64; complex problems use interleaved complex128 (re, im).
+ * Streams are hipStream_t passed as void* (NULL = default stream).  A handle
+ * is bound to one stream and is not thread-safe; calls on one handle must not
+ * overlap.
+ *
+ * Errors.  Functions return a gadi_status.  Negative values are errors and
+ * leave the handle usable (argument errors are detected before any device
+ * work).  GADI_ERR_HIP carries the HIP error text in gadi_last_error().
+ * Positive values are numerical outcomes of a finished solve.
+ */
+#ifndef GADI_H
+#define GADI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gadi_status;
+
+enum {
+  GADI_OK = 0,              /* converged: criterion <= tol                         */
+  GADI_NOT_CONVERGED = 1,   /* reached max_outer sweeps                            */
+  GADI_STAGNATED = 2,       /* BE did not drop below 0.99x its reference in
+                               stag_window sweeps (Section 4.3, step 3)            */
+  GADI_DIVERGED = 3,        /* BE not finite, or above div_factor * best BE        */
+  GADI_RUNNING = 4,         /* asynchronous solve still in progress                */
+  GADI_ERR_INVALID_ARG = -1,
+  GADI_ERR_UNSUPPORTED = -2,
+  GADI_ERR_WORKSPACE = -3,  /* workspace missing, misaligned or too small          */
+  GADI_ERR_HIP = -4,
+  GADI_ERR_CAPACITY = -5,   /* batch full, or budget exceeded                      */
+  GADI_ERR_STATE = -6       /* call not valid in the handle's current state        */
+};
+
+/* Precision of a stage of Algorithm 1 (u_r, u, u_s; Section 2.3, Table 1).
+ * GADI_BF16 means BF16 storage with FP32 arithmetic (Section 5.1). */
+typedef enum { GADI_F64 = 0, GADI_F32 = 1, GADI_BF16 = 2 } gadi_prec;
+
+/* The operator A (matrix-free).  At interior grid point p:
+ *   (A u)_p = center*u_p + sum_d ( lo[d]*u_{p-e_d} + hi[d]*u_{p+e_d} )
+ *             + i*shift_im*u_p                          (is_complex only)
+ * with u = 0 outside the grid.  2D: dim = 2, n[2] = 1, lo[2] = hi[2] = 0.
+ * Complex problems must have a symmetric real part (lo[d] == hi[d]) so that
+ * N = i*shift_im*I and the S solve is pointwise (Section 5.4's problem class);
+ * otherwise GADI_ERR_UNSUPPORTED. */
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int32_t is_complex;   /* 0 real float64; 1 complex128 interleaved */
+  int64_t n[3];         /* interior points per axis (x, y, z), each >= 1 */
+  double center;
+  double lo[3];
+  double hi[3];
+  double shift_im;
+} gadi_stencil;
+
+/* Solver parameters.  Fill with gadi_params_default() first. */
+typedef struct {
+  double alpha;            /* regularization, > 0 (Section 2.1)                          */
+  double omega;            /* extrapolation, in [0, 2) (Section 2.1)                      */
+  int32_t u_r, u, u_s;     /* precisions; u_r and u must be GADI_F64                      */
+  int32_t stop_on_relres;  /* 0: backward error (default); 1: ||r||/||r0||                */
+  double tol;              /* outer target, e.g. 1e-10                                    */
+  int64_t max_outer;       /* sweep cap -> GADI_NOT_CONVERGED                             */
+  int32_t stag_window;     /* outer stagnation window in sweeps (0: off), default 200     */
+  int32_t inner_stag_window; /* inner early stop: no 1% progress in this many its (0: off) */
+  double div_factor;       /* divergence if BE > div_factor * min BE (0: off), default 1e3 */
+  double inner_tol_h;      /* relative-residual tolerance of CG on H (Section 5.1)        */
+  double inner_tol_s;      /* relative-residual tolerance of CGNE on S                     */
+  int32_t max_inner_h;     /* iteration caps of the inner solves                          */
+  int32_t max_inner_s;
+  int32_t fixed_inner_h;   /* > 0: run exactly this many CG iterations (mirror tests)     */
+  int32_t fixed_inner_s;
+  double normA;            /* > 0: use this ||A||_2; 0: estimate at gadi_create           */
+  int32_t norm_iters;      /* power iterations for the estimate (default 100)             */
+  int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0: library default        */
+  int32_t tile_chunk;      /* planes per tile along the marching axis; 0: default          */
+  int32_t reserved;
+} gadi_params;
+
+/* Outcome of a solve. */
+typedef struct {
+  int64_t outer;        /* sweeps performed (x returned is x^(outer))                */
+  int64_t inner_h;      /* total CG iterations on H                                  */
+  int64_t inner_s;      /* total CGNE iterations on S (0 for complex problems)       */
+  double be;            /* backward error of the returned x (FP64, as computed)      */
+  double relres;        /* ||r|| / ||r0||                                             */
+  double normA;         /* ||A||_2 used in the backward error                        */
+  double normb;
+  double ms;            /* device time of the solve (hipEvent), milliseconds         */
+  int32_t status;       /* GADI_OK .. GADI_DIVERGED                                   */
+  int32_t steps;        /* device steps launched (including idle steps at the end)   */
+} gadi_report;
+
+typedef struct gadi_handle gadi_handle;
+typedef struct gadi_batch gadi_batch;
+
+/* Library version string. */
+const char* gadi_version(void);
+/* Text of a status code. */
+const char* gadi_status_string(gadi_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* gadi_last_error(void);
+
+/* Default parameters: alpha 0.5, omega 1, u_r = u = F64, u_s = F64, BE stop,
+ * tol 1e-10, max_outer 20000, stag_window 200, inner_stag_window 20,
+ * div_factor 1e3, inner tolerances 1e-3, caps 2000, normA estimated. */
+void gadi_params_default(gadi_params* p);
+
+/* Bytes of device workspace a handle needs for (stencil, params); 256-byte
+ * alignment is required.  Returns GADI_ERR_INVALID_ARG / UNSUPPORTED for
+ * invalid or unsupported problems. */
+gadi_status gadi_workspace_bytes(const gadi_stencil* st, const gadi_params* p, size_t* bytes);
+
+/* Create a solver handle.  Validates arguments, lays out the workspace
+ * (which must stay alive until gadi_destroy), zero-fills it, uploads the
+ * operator description and, when p->normA == 0, estimates ||A||_2 by power
+ * iteration on A^T A (a lower bound, so the backward error is conservative).
+ * Synchronizes the stream before returning. */
+gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_stream,
+                        void* d_workspace, size_t ws_bytes, gadi_handle** out);
+
+/* Change alpha / omega / tolerances of an existing handle (same operator and
+ * precisions).  Must not be called while a solve is running. */
+gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p);
+
+/* Solve A x = b.  d_b: device b (n values); d_x: device x, in: x^(0) (zeros
+ * reproduce Algorithm 1), out: the returned iterate.  out may be NULL.
+ * h_history (nullable, host, length 4*(max_outer+1)) receives per sweep k:
+ * [BE_k, relres_k, CG iterations of sweep k, CGNE iterations of sweep k].
+ * Blocks until the solve is finished. */
+gadi_status gadi_solve(gadi_handle* h, const void* d_b, void* d_x, gadi_report* out,
+                       double* h_history);
+
+/* Start a solve without waiting (same arguments as gadi_solve); progress it
+ * with gadi_query.  b and x must stay alive until the solve has finished. */
+gadi_status gadi_solve_async(gadi_handle* h, const void* d_b, void* d_x);
+
+/* Advance / poll an asynchronous solve.  wait = 0: enqueue more device
+ * steps if needed and return GADI_RUNNING while unfinished; wait = 1: run
+ * to completion.  When finished, fills *out (nullable) and h_history. */
+gadi_status gadi_query(gadi_handle* h, int32_t wait, gadi_report* out, double* h_history);
+
+/* ||A||_2 in use by the handle (given or estimated). */
+gadi_status gadi_get_norm(gadi_handle* h, double* normA);
+
+/* Frees host state only; the caller frees the workspace afterwards. */
+gadi_status gadi_destroy(gadi_handle* h);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1) in float64 / complex128
+ * on dense vectors (the operator of Section 5, e.g. to form b = A x_true).
+ * Asynchronous on the stream.  x and y must not overlap. */
+gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x, void* d_y,
+                       int32_t transpose);
+
+/* ---- batched execution ------------------------------------------------------
+ * A batch advances many handles together: one device step launch per
+ * (precision, dimension, tile shape) class moves every member by one phase
+ * of its own state machine.  Steps are captured once in a hipGraph and
+ * relaunched.  Results of a member do not depend on the other members
+ * (each system keeps its own reduction order).  Members keep their Krylov
+ * state resident in their own workspaces. */
+
+/* Device workspace of a batch able to hold max_systems members. */
+gadi_status gadi_batch_workspace_bytes(int32_t max_systems, size_t* bytes);
+
+gadi_status gadi_batch_create(int32_t max_systems, void* hip_stream, void* d_workspace,
+                              size_t ws_bytes, gadi_batch** out);
+
+/* Add a handle with its b and x (x^(0) in, result out); starts its solve.
+ * The handle must use the batch's stream and must not be solving elsewhere.
+ * *slot receives the member's slot id. */
+gadi_status gadi_batch_add(gadi_batch* b, gadi_handle* h, const void* d_b, void* d_x,
+                           int32_t* slot);
+
+/* Launch nsteps device steps for all members (asynchronous). */
+gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps);
+
+/* Synchronize and report which members are finished: done[i] = 1 for slot i
+ * if finished (length max_systems, nullable).  Returns the number of active
+ * (unfinished) members through *active. */
+gadi_status gadi_batch_poll(gadi_batch* b, int32_t* done, int32_t* active);
+
+/* Report of a finished member, then remove it from the batch. */
+gadi_status gadi_batch_remove(gadi_batch* b, int32_t slot, gadi_report* out, double* h_history);
+
+gadi_status gadi_batch_destroy(gadi_batch* b);
+
+/* ---- autotuning -----------------------------------------------------------
+ * Choose the tile shape of the step kernels (rows per wave in 3D, planes per
+ * chunk along the marching axis) for this stencil's shape and precision by
+ * timing candidate shapes on the device: for each one a handle is created in
+ * the caller's workspace (ws_bytes must cover the largest candidate layout;
+ * gadi_workspace_bytes with tile_chunk = 2 is an upper bound), the state
+ * machine is armed with d_b / d_x (read only; x is not written) and a run of
+ * CG iterations on H is timed with hipEvents.  Returns the fastest shape in
+ * *ry, *chunk and its time per CG iteration in *best_us.  Results are cached
+ * per (dimension, grid, precision) for the process and, when the
+ * environment variable GADI_TUNE_CACHE names a file, across processes. */
+gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* p, void* hip_stream,
+                          void* d_workspace, size_t ws_bytes, const void* d_b, void* d_x,
+                          int32_t* ry, int32_t* chunk, double* best_us);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GADI_H */

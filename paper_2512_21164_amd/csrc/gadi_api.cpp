@@ -1,0 +1,899 @@
+// Host runtime and C ABI of the GADI library (declared in include/gadi.h).
+//
+// A handle owns no device memory: its workspace is carved into the system
+// descriptor, the control block of the device state machine, reduction
+// partials, the sweep history and the vectors.  A solve arms the state
+// machine (IMPORT) and then launches device steps in chunks, reading the
+// control block back between chunks until the machine reports DONE.  All
+// decisions of Algorithm 1 (convergence, inner stopping, CG scalars) are
+// taken on the device, so the host never waits on a dot product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/gadi.h"
+#include "gadi_internal.h"
+#include "gadi_launch.h"
+
+using namespace gadi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gadi_status fail(gadi_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(GADI_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+constexpr int64_t kHistCap = 1 << 20;
+
+struct Layout {
+  int dim, cplx, us;
+  int nx, ny, nz;
+  int64_t P, nvec, n;
+  int ny_plane, nm, RY, L, nwy, nmc;
+  int64_t sy, sm;
+  Tiling ti, to;
+  int max_tiles;
+  int64_t hist_len;
+  size_t welem, selem;   // bytes of an FP64 element and of a u_s element
+  // offsets
+  size_t o_desc, o_ctl, o_counter, o_table, o_partials, o_hist, o_x0, o_x1, o_b, o_vs[4], total;
+};
+
+int us_bytes(int us, int cplx) {
+  int b = us == US_F64 ? 8 : (us == US_F32 ? 4 : 2);
+  return cplx ? 2 * b : b;
+}
+
+Tiling make_tiling(const Layout& l, int V) {
+  Tiling t;
+  t.V = V;
+  t.nwx = (int)((l.nx + 64 * V - 1) / (64 * V));
+  int64_t nwave = (int64_t)t.nwx * l.nwy * l.nmc;
+  t.nwave = (int)nwave;
+  t.ntiles = (int)((nwave + 3) / 4);
+  return t;
+}
+
+gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
+  if (!st || !p) return fail(GADI_ERR_INVALID_ARG, "null stencil or params");
+  if (st->dim != 2 && st->dim != 3) return fail(GADI_ERR_INVALID_ARG, "dim must be 2 or 3");
+  for (int d = 0; d < 3; ++d)
+    if (st->n[d] < 1) return fail(GADI_ERR_INVALID_ARG, "grid sizes must be >= 1");
+  if (st->dim == 2 && st->n[2] != 1) return fail(GADI_ERR_INVALID_ARG, "2D problems need n[2] == 1");
+  if (st->n[0] > (1 << 24) || st->n[1] > (1 << 24) || st->n[2] > (1 << 24))
+    return fail(GADI_ERR_UNSUPPORTED, "grid side above 2^24");
+  const double nn = (double)st->n[0] * (double)st->n[1] * (double)st->n[2];
+  if (nn > 4.0e9) return fail(GADI_ERR_UNSUPPORTED, "more than 4e9 unknowns");
+  if (!std::isfinite(st->center) || !std::isfinite(st->shift_im))
+    return fail(GADI_ERR_INVALID_ARG, "non-finite stencil coefficient");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(st->lo[d]) || !std::isfinite(st->hi[d]))
+      return fail(GADI_ERR_INVALID_ARG, "non-finite stencil coefficient");
+  if (st->is_complex) {
+    for (int d = 0; d < st->dim; ++d)
+      if (st->lo[d] != st->hi[d])
+        return fail(GADI_ERR_UNSUPPORTED, "complex problems need a symmetric real stencil (lo == hi)");
+  } else if (st->shift_im != 0.0) {
+    return fail(GADI_ERR_INVALID_ARG, "shift_im needs is_complex = 1");
+  }
+  if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(GADI_ERR_INVALID_ARG, "alpha must be > 0");
+  if (!(p->omega >= 0.0 && p->omega < 2.0)) return fail(GADI_ERR_INVALID_ARG, "omega must lie in [0, 2)");
+  if (p->u_r != GADI_F64 || p->u != GADI_F64)
+    return fail(GADI_ERR_UNSUPPORTED, "u_r and u must be GADI_F64");
+  if (p->u_s < GADI_F64 || p->u_s > GADI_BF16) return fail(GADI_ERR_INVALID_ARG, "unknown u_s");
+  if (!(p->tol >= 0.0)) return fail(GADI_ERR_INVALID_ARG, "tol must be >= 0");
+  if (p->max_outer < 0) return fail(GADI_ERR_INVALID_ARG, "max_outer must be >= 0");
+  if (p->max_inner_h < 1 || p->max_inner_s < 1) return fail(GADI_ERR_INVALID_ARG, "inner caps must be >= 1");
+  if (!(p->inner_tol_h >= 0.0) || !(p->inner_tol_s >= 0.0)) return fail(GADI_ERR_INVALID_ARG, "inner tolerances must be >= 0");
+  if (p->fixed_inner_h < 0 || p->fixed_inner_s < 0 || p->stag_window < 0 || p->inner_stag_window < 0)
+    return fail(GADI_ERR_INVALID_ARG, "negative iteration parameter");
+  if (!(p->normA >= 0.0) || !std::isfinite(p->normA)) return fail(GADI_ERR_INVALID_ARG, "normA must be >= 0");
+  if (p->normA == 0.0 && p->norm_iters < 1) return fail(GADI_ERR_INVALID_ARG, "norm_iters must be >= 1");
+  if (p->tile_ry != 0 && p->tile_ry != 1 && p->tile_ry != 2 && p->tile_ry != 4)
+    return fail(GADI_ERR_INVALID_ARG, "tile_ry must be 0, 1, 2 or 4");
+  if (p->tile_chunk < 0 || p->tile_chunk > 4096) return fail(GADI_ERR_INVALID_ARG, "tile_chunk out of range");
+  if (!(p->div_factor >= 0.0)) return fail(GADI_ERR_INVALID_ARG, "div_factor must be >= 0");
+  return GADI_OK;
+}
+
+int default_ry(int us, int cplx) {
+  if (cplx) return 1;
+  return us == US_F64 ? 2 : (us == US_F32 ? 2 : 1);
+}
+
+Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
+  Layout l{};
+  l.dim = st->dim; l.cplx = st->is_complex ? 1 : 0; l.us = p->u_s;
+  l.nx = (int)st->n[0]; l.ny = (int)st->n[1]; l.nz = (int)st->n[2];
+  l.P = (l.nx + 7) / 8 * 8;
+  l.n = (int64_t)l.nx * l.ny * l.nz;
+  l.nvec = l.P * l.ny * l.nz;
+  if (l.dim == 2) {
+    l.ny_plane = 1; l.nm = l.ny; l.sy = l.P; l.sm = l.P; l.RY = 1;
+  } else {
+    l.ny_plane = l.ny; l.nm = l.nz; l.sy = l.P; l.sm = l.P * l.ny;
+    l.RY = p->tile_ry ? p->tile_ry : default_ry(l.us, l.cplx);
+  }
+  l.nwy = (l.dim == 2) ? 1 : (l.ny_plane + l.RY - 1) / l.RY;
+  const int vi = 16 / us_bytes(l.us, l.cplx);
+  if (p->tile_chunk > 0) {
+    l.L = p->tile_chunk;
+  } else {
+    // about 8192 wave tiles (32 per CU) for large grids, 4..64 planes each
+    const int64_t nwx = (l.nx + 64 * vi - 1) / (64 * vi);
+    const int64_t per_plane = nwx * l.nwy;
+    int64_t L = (per_plane * l.nm + 8191) / 8192;
+    L = std::max<int64_t>(4, std::min<int64_t>(64, L));
+    l.L = (int)L;
+  }
+  l.nmc = (l.nm + l.L - 1) / l.L;
+  l.ti = make_tiling(l, vi);
+  l.to = make_tiling(l, l.cplx ? 1 : 2);
+  l.max_tiles = std::max(l.ti.ntiles, l.to.ntiles);
+  l.hist_len = std::min<int64_t>(p->max_outer + 1, kHistCap);
+  l.welem = l.cplx ? 16 : 8;
+  l.selem = us_bytes(l.us, l.cplx);
+  size_t o = 0;
+  l.o_desc = o; o = align_up(o + sizeof(GadiDesc));
+  l.o_ctl = o; o = align_up(o + sizeof(GadiCtl));
+  l.o_counter = o; o = align_up(o + 64);
+  l.o_table = o; o = align_up(o + sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t) + 64);
+  l.o_partials = o; o = align_up(o + 4 * sizeof(double) * (size_t)l.max_tiles);
+  l.o_hist = o; o = align_up(o + 4 * sizeof(double) * (size_t)l.hist_len);
+  l.o_x0 = o; o = align_up(o + l.welem * (size_t)l.nvec);
+  l.o_x1 = o; o = align_up(o + l.welem * (size_t)l.nvec);
+  l.o_b = o; o = align_up(o + l.welem * (size_t)l.nvec);
+  for (int i = 0; i < 4; ++i) { l.o_vs[i] = o; o = align_up(o + l.selem * (size_t)l.nvec); }
+  l.total = o;
+  return l;
+}
+
+void fill_desc(GadiDesc& d, const Layout& l, const gadi_stencil* st, const gadi_params* p, char* ws) {
+  std::memset(&d, 0, sizeof(d));
+  d.dim = l.dim; d.cplx = l.cplx; d.us = l.us; d.RY = l.RY;
+  d.nx = l.nx; d.ny = l.ny; d.nz = l.nz; d.L = l.L;
+  d.P = l.P; d.n = l.n; d.nvec = l.nvec;
+  d.ny_plane = l.ny_plane; d.nm = l.nm; d.nwy = l.nwy; d.nmc = l.nmc;
+  d.sy = l.sy; d.sm = l.sm;
+  d.ti = l.ti; d.to = l.to; d.max_tiles = l.max_tiles;
+  // kernel axis order: 0 = x, 1 = in-plane y (3D), 2 = marching axis (2D: y, 3D: z)
+  const int map2[3] = {0, -1, 1}, map3[3] = {0, 1, 2};
+  const int* mp = l.dim == 2 ? map2 : map3;
+  d.cA = st->center;
+  d.shift_im = l.cplx ? st->shift_im : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int s = mp[a];
+    const double lo = s >= 0 ? st->lo[s] : 0.0, hi = s >= 0 ? st->hi[s] : 0.0;
+    d.loA[a] = lo; d.hiA[a] = hi;
+    d.mH[a] = 0.5 * (lo + hi);           // M = (A + A^T)/2
+    d.nuS[a] = 0.5 * (hi - lo);          // N = (A - A^T)/2: N(i, i+e) = (hi - lo)/2
+  }
+  d.alpha = p->alpha;
+  d.cH = p->alpha + st->center;
+  d.gamma = (2.0 - p->omega) * p->alpha;
+  if (l.cplx) {
+    const double den = p->alpha * p->alpha + st->shift_im * st->shift_im;
+    d.g_re = d.gamma * p->alpha / den;
+    d.g_im = -d.gamma * st->shift_im / den;
+  }
+  d.cAf = (float)d.cA; d.shift_imf = (float)d.shift_im;
+  for (int a = 0; a < 3; ++a) {
+    d.loAf[a] = (float)d.loA[a]; d.hiAf[a] = (float)d.hiA[a];
+    d.mHf[a] = (float)d.mH[a]; d.nuSf[a] = (float)d.nuS[a];
+  }
+  d.cHf = (float)d.cH; d.alphaf = (float)d.alpha; d.gammaf = (float)d.gamma;
+  d.tol = p->tol; d.div_factor = p->div_factor;
+  d.inner_tol_h = p->inner_tol_h; d.inner_tol_s = p->inner_tol_s;
+  d.max_outer = p->max_outer;
+  d.stop_relres = p->stop_on_relres ? 1 : 0;
+  d.stag_window = p->stag_window; d.inner_stag = p->inner_stag_window;
+  d.max_inner_h = p->max_inner_h; d.max_inner_s = p->max_inner_s;
+  d.fixed_h = p->fixed_inner_h; d.fixed_s = p->fixed_inner_s;
+  d.hist_len = (int32_t)l.hist_len;
+  d.xbuf[0] = reinterpret_cast<double*>(ws + l.o_x0);
+  d.xbuf[1] = reinterpret_cast<double*>(ws + l.o_x1);
+  d.bpad = reinterpret_cast<double*>(ws + l.o_b);
+  for (int i = 0; i < 4; ++i) d.vs[i] = ws + l.o_vs[i];
+  d.user_b = nullptr; d.user_x = nullptr;
+  d.partials = reinterpret_cast<double*>(ws + l.o_partials);
+  d.counter = reinterpret_cast<uint32_t*>(ws + l.o_counter);
+  d.ctl = reinterpret_cast<GadiCtl*>(ws + l.o_ctl);
+  d.hist = reinterpret_cast<double*>(ws + l.o_hist);
+}
+
+int kernel_class_key(const Layout& l) { return ((l.us * 2 + l.cplx) * 4 + l.dim) * 8 + l.RY; }
+
+}  // namespace
+
+struct gadi_handle {
+  gadi_stencil st;
+  gadi_params p;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  Layout lay;
+  GadiDesc hdesc;
+  GadiDesc* d_desc;
+  GadiCtl* d_ctl;
+  BatchTable* d_table;
+  GadiCtl* h_ctl;        // pinned readback buffer
+  double normA;
+  hipEvent_t ev0, ev1;
+  // asynchronous solve
+  int running;
+  int chunk;
+  int64_t steps;
+  int64_t max_steps;
+  int in_batch;
+};
+
+namespace {
+
+gadi_status read_ctl(gadi_handle* h) {
+  HIP_TRY(hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(GadiCtl), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return GADI_OK;
+}
+
+gadi_status launch_steps(gadi_handle* h, int count) {
+  const int grid = (h->lay.max_tiles + 7) / 8 * 8;
+  for (int i = 0; i < count; ++i) {
+    hipError_t e = launch_step(h->lay.us, h->lay.cplx, h->lay.dim, h->lay.RY, h->d_table, grid, h->stream);
+    if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("step launch: ") + hipGetErrorString(e));
+  }
+  h->steps += count;
+  return GADI_OK;
+}
+
+// Upper bound on the device steps of one solve (the state machine always ends).
+int64_t step_bound(const gadi_params& p, int cplx) {
+  const int64_t ih = p.fixed_inner_h > 0 ? p.fixed_inner_h : p.max_inner_h;
+  const int64_t is = cplx ? 0 : (p.fixed_inner_s > 0 ? p.fixed_inner_s : p.max_inner_s);
+  const int64_t per = 2 * ih + 2 * is + 2;
+  return (p.max_outer + 1) * per + 16;
+}
+
+gadi_status run_to(gadi_handle* h, int target_phase, bool wait, int64_t bound) {
+  for (;;) {
+    gadi_status s = launch_steps(h, h->chunk);
+    if (s != GADI_OK) return s;
+    s = read_ctl(h);
+    if (s != GADI_OK) return s;
+    if (h->h_ctl->phase == target_phase) return GADI_OK;
+    if (h->steps > bound) return fail(GADI_ERR_STATE, "device state machine did not finish within its step bound");
+    h->chunk = std::min(h->chunk * 2, 256);
+    if (!wait) return GADI_RUNNING;
+  }
+}
+
+void fill_report(gadi_handle* h, gadi_report* out) {
+  if (!out) return;
+  const GadiCtl& c = *h->h_ctl;
+  out->outer = c.k;
+  out->inner_h = c.inner_h_total;
+  out->inner_s = c.inner_s_total;
+  out->be = c.be;
+  out->relres = c.relres;
+  out->normA = c.normA;
+  out->normb = c.normb;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) ms = -1.f;
+  out->ms = ms;
+  out->status = c.status;
+  out->steps = (int32_t)std::min<int64_t>(h->steps, INT32_MAX);
+}
+
+gadi_status copy_history(gadi_handle* h, double* hist) {
+  if (!hist) return GADI_OK;
+  const int64_t n = std::min<int64_t>((int64_t)h->h_ctl->k + 1, h->lay.hist_len);
+  HIP_TRY(hipMemcpy(hist, h->ws + h->lay.o_hist, (size_t)n * 4 * sizeof(double), hipMemcpyDeviceToHost));
+  return GADI_OK;
+}
+
+gadi_status start_solve(gadi_handle* h, const void* b, void* x) {
+  if (!b || !x) return fail(GADI_ERR_INVALID_ARG, "null b or x");
+  if (h->running || h->in_batch) return fail(GADI_ERR_STATE, "a solve is already running on this handle");
+  HIP_TRY(hipEventRecord(h->ev0, h->stream));
+  HIP_TRY(launch_set_io(h->d_desc, static_cast<const double*>(b), static_cast<double*>(x), h->stream));
+  HIP_TRY(launch_set_phase(h->d_ctl, PH_IMPORT, 0, 0.0, h->stream));
+  h->steps = 0;
+  h->chunk = 16;
+  h->max_steps = step_bound(h->p, h->lay.cplx);
+  h->running = 1;
+  return GADI_OK;
+}
+
+gadi_status finish_solve(gadi_handle* h, gadi_report* out, double* hist) {
+  HIP_TRY(hipEventRecord(h->ev1, h->stream));
+  HIP_TRY(hipEventSynchronize(h->ev1));
+  h->running = 0;
+  fill_report(h, out);
+  gadi_status s = copy_history(h, hist);
+  if (s != GADI_OK) return s;
+  return h->h_ctl->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gadi_version(void) { return "gadi-mi355x 0.1 (gfx950)"; }
+
+const char* gadi_status_string(gadi_status s) {
+  switch (s) {
+    case GADI_OK: return "OK";
+    case GADI_NOT_CONVERGED: return "NOT_CONVERGED";
+    case GADI_STAGNATED: return "STAGNATED";
+    case GADI_DIVERGED: return "DIVERGED";
+    case GADI_RUNNING: return "RUNNING";
+    case GADI_ERR_INVALID_ARG: return "ERR_INVALID_ARG";
+    case GADI_ERR_UNSUPPORTED: return "ERR_UNSUPPORTED";
+    case GADI_ERR_WORKSPACE: return "ERR_WORKSPACE";
+    case GADI_ERR_HIP: return "ERR_HIP";
+    case GADI_ERR_CAPACITY: return "ERR_CAPACITY";
+    case GADI_ERR_STATE: return "ERR_STATE";
+    default: return "UNKNOWN";
+  }
+}
+
+const char* gadi_last_error(void) { return g_last_error.c_str(); }
+
+void gadi_params_default(gadi_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = 0.5;
+  p->omega = 1.0;
+  p->u_r = GADI_F64; p->u = GADI_F64; p->u_s = GADI_F64;
+  p->stop_on_relres = 0;
+  p->tol = 1e-10;
+  p->max_outer = 20000;
+  p->stag_window = 200;
+  p->inner_stag_window = 20;
+  p->div_factor = 1e3;
+  p->inner_tol_h = 1e-3;
+  p->inner_tol_s = 1e-3;
+  p->max_inner_h = 2000;
+  p->max_inner_s = 2000;
+  p->fixed_inner_h = 0;
+  p->fixed_inner_s = 0;
+  p->normA = 0.0;
+  p->norm_iters = 100;
+  p->tile_ry = 0;
+  p->tile_chunk = 0;
+}
+
+gadi_status gadi_workspace_bytes(const gadi_stencil* st, const gadi_params* p, size_t* bytes) {
+  if (!bytes) return fail(GADI_ERR_INVALID_ARG, "null bytes");
+  gadi_status s = validate(st, p);
+  if (s != GADI_OK) return s;
+  *bytes = make_layout(st, p).total;
+  return GADI_OK;
+}
+
+gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_stream, void* d_workspace,
+                        size_t ws_bytes, gadi_handle** out) {
+  if (!out) return fail(GADI_ERR_INVALID_ARG, "null out");
+  *out = nullptr;
+  gadi_status s = validate(st, p);
+  if (s != GADI_OK) return s;
+  Layout l = make_layout(st, p);
+  if (!d_workspace) return fail(GADI_ERR_WORKSPACE, "null workspace");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return fail(GADI_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < l.total)
+    return fail(GADI_ERR_WORKSPACE, "workspace too small: need " + std::to_string(l.total) + " bytes");
+  gadi_handle* h = new gadi_handle();
+  h->st = *st; h->p = *p;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(d_workspace);
+  h->ws_bytes = ws_bytes;
+  h->lay = l;
+  h->d_desc = reinterpret_cast<GadiDesc*>(h->ws + l.o_desc);
+  h->d_ctl = reinterpret_cast<GadiCtl*>(h->ws + l.o_ctl);
+  h->d_table = reinterpret_cast<BatchTable*>(h->ws + l.o_table);
+  fill_desc(h->hdesc, l, st, p, h->ws);
+  auto cleanup = [&](gadi_status e) { if (h->h_ctl) (void)hipHostFree(h->h_ctl); delete h; return e; };
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(GadiCtl), hipHostMallocDefault) != hipSuccess) {
+    h->h_ctl = nullptr;
+    return cleanup(fail(GADI_ERR_HIP, "pinned host buffer"));
+  }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    return cleanup(fail(GADI_ERR_HIP, "event create"));
+  // single-system table: desc pointer and tile prefix live right after the table header
+  char* tb = h->ws + l.o_table;
+  BatchTable t{};
+  t.nsys = 1;
+  t.total_tiles = l.max_tiles;
+  t.slots = (l.max_tiles + 7) / 8 * 8;
+  t.desc = reinterpret_cast<GadiDesc**>(tb + sizeof(BatchTable));
+  t.tile_start = reinterpret_cast<int32_t*>(tb + sizeof(BatchTable) + sizeof(GadiDesc*));
+  std::vector<char> tbuf(sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t));
+  std::memcpy(tbuf.data(), &t, sizeof(t));
+  std::memcpy(tbuf.data() + sizeof(BatchTable), &h->d_desc, sizeof(GadiDesc*));
+  int32_t ts[2] = {0, l.max_tiles};
+  std::memcpy(tbuf.data() + sizeof(BatchTable) + sizeof(GadiDesc*), ts, sizeof(ts));
+  hipError_t e = hipMemsetAsync(h->ws, 0, l.total, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(GadiDesc), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(tb, tbuf.data(), tbuf.size(), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return cleanup(fail(GADI_ERR_HIP, std::string("workspace init: ") + hipGetErrorString(e)));
+  if (p->normA > 0.0) {
+    h->normA = p->normA;
+    e = launch_set_norm(h->d_ctl, p->normA, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return cleanup(fail(GADI_ERR_HIP, std::string("set norm: ") + hipGetErrorString(e)));
+  } else {
+    // power iteration on A^H A from a checkerboard start (2 steps per iteration)
+    e = launch_set_phase(h->d_ctl, PH_NORM_A, p->norm_iters, 1.0 / std::sqrt((double)l.n), h->stream);
+    if (e != hipSuccess) return cleanup(fail(GADI_ERR_HIP, std::string("set phase: ") + hipGetErrorString(e)));
+    h->steps = 0;
+    s = launch_steps(h, 2 * p->norm_iters);
+    if (s == GADI_OK) s = read_ctl(h);
+    if (s != GADI_OK) return cleanup(s);
+    if (h->h_ctl->phase != PH_IDLE) return cleanup(fail(GADI_ERR_STATE, "norm estimation did not finish"));
+    h->normA = h->h_ctl->normA;
+  }
+  *out = h;
+  return GADI_OK;
+}
+
+gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p) {
+  if (!h || !p) return fail(GADI_ERR_INVALID_ARG, "null handle or params");
+  if (h->running || h->in_batch) return fail(GADI_ERR_STATE, "solve running");
+  gadi_status s = validate(&h->st, p);
+  if (s != GADI_OK) return s;
+  if (p->u_s != h->p.u_s) return fail(GADI_ERR_INVALID_ARG, "u_s cannot change");
+  Layout l = make_layout(&h->st, p);
+  if (l.total > h->ws_bytes || l.max_tiles != h->lay.max_tiles || l.RY != h->lay.RY || l.L != h->lay.L)
+    return fail(GADI_ERR_INVALID_ARG, "new parameters change the workspace layout; create a new handle");
+  GadiDesc d;
+  fill_desc(d, l, &h->st, p, h->ws);
+  HIP_TRY(hipMemcpyAsync(h->d_desc, &d, sizeof(GadiDesc), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->hdesc = d;
+  h->lay = l;
+  const double keep = h->normA;
+  h->p = *p;
+  if (p->normA > 0.0) {
+    h->normA = p->normA;
+    HIP_TRY(launch_set_norm(h->d_ctl, p->normA, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  } else {
+    h->normA = keep;
+  }
+  return GADI_OK;
+}
+
+gadi_status gadi_solve(gadi_handle* h, const void* d_b, void* d_x, gadi_report* out, double* h_history) {
+  if (!h) return fail(GADI_ERR_INVALID_ARG, "null handle");
+  gadi_status s = start_solve(h, d_b, d_x);
+  if (s != GADI_OK) return s;
+  s = run_to(h, PH_DONE, true, h->max_steps);
+  if (s != GADI_OK) { h->running = 0; return s; }
+  return finish_solve(h, out, h_history);
+}
+
+gadi_status gadi_solve_async(gadi_handle* h, const void* d_b, void* d_x) {
+  if (!h) return fail(GADI_ERR_INVALID_ARG, "null handle");
+  gadi_status s = start_solve(h, d_b, d_x);
+  if (s != GADI_OK) return s;
+  return launch_steps(h, h->chunk);
+}
+
+gadi_status gadi_query(gadi_handle* h, int32_t wait, gadi_report* out, double* h_history) {
+  if (!h) return fail(GADI_ERR_INVALID_ARG, "null handle");
+  if (!h->running) return fail(GADI_ERR_STATE, "no solve running");
+  gadi_status s = read_ctl(h);
+  if (s != GADI_OK) return s;
+  if (h->h_ctl->phase != PH_DONE) {
+    s = run_to(h, PH_DONE, wait != 0, h->max_steps);
+    if (s == GADI_RUNNING) return s;
+    if (s != GADI_OK) { h->running = 0; return s; }
+  }
+  return finish_solve(h, out, h_history);
+}
+
+gadi_status gadi_get_norm(gadi_handle* h, double* normA) {
+  if (!h || !normA) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  *normA = h->normA;
+  return GADI_OK;
+}
+
+gadi_status gadi_destroy(gadi_handle* h) {
+  if (!h) return GADI_OK;
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipEventDestroy(h->ev0);
+  (void)hipEventDestroy(h->ev1);
+  if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  delete h;
+  return GADI_OK;
+}
+
+gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x, void* d_y, int32_t transpose) {
+  if (!st || !d_x || !d_y) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  if (st->dim != 2 && st->dim != 3) return fail(GADI_ERR_INVALID_ARG, "dim must be 2 or 3");
+  for (int d = 0; d < 3; ++d)
+    if (st->n[d] < 1) return fail(GADI_ERR_INVALID_ARG, "grid sizes must be >= 1");
+  if (st->dim == 2 && st->n[2] != 1) return fail(GADI_ERR_INVALID_ARG, "2D problems need n[2] == 1");
+  if (d_x == d_y) return fail(GADI_ERR_INVALID_ARG, "x and y must not overlap");
+  double lo[3] = {st->lo[0], st->lo[1], st->dim == 3 ? st->lo[2] : 0.0};
+  double hi[3] = {st->hi[0], st->hi[1], st->dim == 3 ? st->hi[2] : 0.0};
+  HIP_TRY(launch_apply_dense(st->is_complex ? 1 : 0, st->dim, (int)st->n[0], (int)st->n[1], (int)st->n[2], st->center,
+                             lo, hi, st->is_complex ? st->shift_im : 0.0, transpose ? 1 : 0,
+                             static_cast<const double*>(d_x), static_cast<double*>(d_y),
+                             static_cast<hipStream_t>(hip_stream)));
+  return GADI_OK;
+}
+
+}  // extern "C"
+
+// ============================================================== batches
+namespace {
+
+struct ClassGroup {
+  int us, cplx, dim, ry;
+  std::vector<int> slots;     // member slots in this class (sorted)
+  BatchTable* d_table;        // device table header
+  GadiDesc** d_desc;          // device array of descriptor pointers
+  int32_t* d_start;           // device prefix sums
+  int total_tiles;
+};
+
+}  // namespace
+
+struct gadi_batch {
+  int max_sys;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  std::vector<gadi_handle*> member;   // by slot (nullptr = free)
+  std::vector<int> done;              // by slot
+  std::vector<ClassGroup> groups;     // one per kernel class, up to 8
+  bool dirty;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int graph_steps;
+  GadiCtl* h_ctls;                    // pinned readback of all members' control blocks
+};
+
+namespace {
+
+constexpr int kMaxGroups = 8;
+constexpr int kGroupGrid = 2048;     // persistent grid of a batch step launch
+
+size_t group_bytes(int max_sys) {
+  return align_up(sizeof(BatchTable)) + align_up(sizeof(GadiDesc*) * (size_t)max_sys) +
+         align_up(sizeof(int32_t) * (size_t)(max_sys + 1));
+}
+
+gadi_status rebuild_tables(gadi_batch* b) {
+  // group active members by kernel class and upload per-class tables
+  std::map<int, std::vector<int>> by;
+  for (int i = 0; i < b->max_sys; ++i)
+    if (b->member[i] && !b->done[i]) by[kernel_class_key(b->member[i]->lay)].push_back(i);
+  if ((int)by.size() > kMaxGroups) return fail(GADI_ERR_CAPACITY, "too many kernel classes in one batch");
+  b->groups.clear();
+  int gi = 0;
+  for (auto& kv : by) {
+    ClassGroup g{};
+    const Layout& l0 = b->member[kv.second[0]]->lay;
+    g.us = l0.us; g.cplx = l0.cplx; g.dim = l0.dim; g.ry = l0.RY;
+    g.slots = kv.second;
+    char* base = b->ws + gi * group_bytes(b->max_sys);
+    g.d_table = reinterpret_cast<BatchTable*>(base);
+    g.d_desc = reinterpret_cast<GadiDesc**>(base + align_up(sizeof(BatchTable)));
+    g.d_start = reinterpret_cast<int32_t*>(base + align_up(sizeof(BatchTable)) +
+                                           align_up(sizeof(GadiDesc*) * (size_t)b->max_sys));
+    std::vector<GadiDesc*> descs;
+    std::vector<int32_t> start{0};
+    for (int s : g.slots) {
+      descs.push_back(b->member[s]->d_desc);
+      start.push_back(start.back() + b->member[s]->lay.max_tiles);
+    }
+    g.total_tiles = start.back();
+    BatchTable t{};
+    t.nsys = (int)g.slots.size();
+    t.total_tiles = g.total_tiles;
+    t.slots = (g.total_tiles + 7) / 8 * 8;
+    t.desc = g.d_desc;
+    t.tile_start = g.d_start;
+    HIP_TRY(hipMemcpyAsync(g.d_table, &t, sizeof(t), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(g.d_desc, descs.data(), descs.size() * sizeof(GadiDesc*), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(g.d_start, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    b->groups.push_back(g);
+    ++gi;
+  }
+  // pageable sources: make sure the copies have consumed them
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->dirty = false;
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return GADI_OK;
+}
+
+int group_grid(const ClassGroup& g) {
+  const int slots = (g.total_tiles + 7) / 8 * 8;
+  return std::min(slots, kGroupGrid);
+}
+
+gadi_status launch_groups(gadi_batch* b, int nsteps) {
+  for (int s = 0; s < nsteps; ++s)
+    for (auto& g : b->groups) {
+      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, g.d_table, group_grid(g), b->stream);
+      if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("batch step: ") + hipGetErrorString(e));
+    }
+  return GADI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gadi_status gadi_batch_workspace_bytes(int32_t max_systems, size_t* bytes) {
+  if (!bytes || max_systems < 1) return fail(GADI_ERR_INVALID_ARG, "bad arguments");
+  *bytes = kMaxGroups * group_bytes(max_systems);
+  return GADI_OK;
+}
+
+gadi_status gadi_batch_create(int32_t max_systems, void* hip_stream, void* d_workspace, size_t ws_bytes,
+                              gadi_batch** out) {
+  if (!out || max_systems < 1) return fail(GADI_ERR_INVALID_ARG, "bad arguments");
+  *out = nullptr;
+  size_t need = kMaxGroups * group_bytes(max_systems);
+  if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return fail(GADI_ERR_WORKSPACE, "bad workspace");
+  if (ws_bytes < need) return fail(GADI_ERR_WORKSPACE, "batch workspace too small");
+  gadi_batch* b = new gadi_batch();
+  b->max_sys = max_systems;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->ws = static_cast<char*>(d_workspace);
+  b->ws_bytes = ws_bytes;
+  b->member.assign(max_systems, nullptr);
+  b->done.assign(max_systems, 0);
+  b->dirty = true;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->graph_steps = 0;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_ctls), sizeof(GadiCtl) * (size_t)max_systems,
+                    hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return fail(GADI_ERR_HIP, "pinned host buffer");
+  }
+  *out = b;
+  return GADI_OK;
+}
+
+gadi_status gadi_batch_add(gadi_batch* b, gadi_handle* h, const void* d_b, void* d_x, int32_t* slot) {
+  if (!b || !h || !d_b || !d_x) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  if (h->stream != b->stream) return fail(GADI_ERR_INVALID_ARG, "handle and batch use different streams");
+  if (h->running || h->in_batch) return fail(GADI_ERR_STATE, "handle busy");
+  int free_slot = -1;
+  for (int i = 0; i < b->max_sys; ++i)
+    if (!b->member[i]) { free_slot = i; break; }
+  if (free_slot < 0) return fail(GADI_ERR_CAPACITY, "batch full");
+  gadi_status s = start_solve(h, d_b, d_x);
+  if (s != GADI_OK) return s;
+  h->running = 0;          // progress is driven by the batch
+  h->in_batch = 1;
+  b->member[free_slot] = h;
+  b->done[free_slot] = 0;
+  b->dirty = true;
+  if (slot) *slot = free_slot;
+  return GADI_OK;
+}
+
+gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps) {
+  if (!b || nsteps < 0) return fail(GADI_ERR_INVALID_ARG, "bad arguments");
+  if (b->dirty) {
+    gadi_status s = rebuild_tables(b);
+    if (s != GADI_OK) return s;
+  }
+  if (b->groups.empty() || nsteps == 0) return GADI_OK;
+  // capture a graph of `nsteps` steps once per membership and relaunch it
+  if (!b->exec || b->graph_steps != nsteps) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    gadi_status s = launch_groups(b, nsteps);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (s != GADI_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+    if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_steps = nsteps;
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  for (int i = 0; i < b->max_sys; ++i)
+    if (b->member[i] && !b->done[i]) b->member[i]->steps += nsteps;
+  return GADI_OK;
+}
+
+gadi_status gadi_batch_poll(gadi_batch* b, int32_t* done, int32_t* active) {
+  if (!b) return fail(GADI_ERR_INVALID_ARG, "null batch");
+  for (int i = 0; i < b->max_sys; ++i) {
+    gadi_handle* h = b->member[i];
+    if (!h || b->done[i]) continue;
+    HIP_TRY(hipMemcpyAsync(&b->h_ctls[i], h->d_ctl, sizeof(GadiCtl), hipMemcpyDeviceToHost, b->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int act = 0;
+  bool changed = false;
+  for (int i = 0; i < b->max_sys; ++i) {
+    gadi_handle* h = b->member[i];
+    if (!h) { if (done) done[i] = 0; continue; }
+    if (!b->done[i] && b->h_ctls[i].phase == PH_DONE) {
+      b->done[i] = 1;
+      changed = true;
+      *h->h_ctl = b->h_ctls[i];
+      HIP_TRY(hipEventRecord(h->ev1, b->stream));
+    }
+    if (done) done[i] = b->done[i];
+    if (!b->done[i]) ++act;
+  }
+  if (changed) b->dirty = true;
+  if (active) *active = act;
+  return GADI_OK;
+}
+
+gadi_status gadi_batch_remove(gadi_batch* b, int32_t slot, gadi_report* out, double* h_history) {
+  if (!b || slot < 0 || slot >= b->max_sys || !b->member[slot]) return fail(GADI_ERR_INVALID_ARG, "bad slot");
+  gadi_handle* h = b->member[slot];
+  if (!b->done[slot]) return fail(GADI_ERR_STATE, "member not finished");
+  HIP_TRY(hipEventSynchronize(h->ev1));
+  fill_report(h, out);
+  gadi_status s = copy_history(h, h_history);
+  h->in_batch = 0;
+  b->member[slot] = nullptr;
+  b->done[slot] = 0;
+  b->dirty = true;
+  if (s != GADI_OK) return s;
+  return h->h_ctl->status;
+}
+
+gadi_status gadi_batch_destroy(gadi_batch* b) {
+  if (!b) return GADI_OK;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto* h : b->member)
+    if (h) h->in_batch = 0;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->h_ctls) (void)hipHostFree(b->h_ctls);
+  delete b;
+  return GADI_OK;
+}
+
+}  // extern "C"
+
+// ============================================================== autotuning
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+std::string tune_key(const gadi_stencil* st, const gadi_params* p) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "d%d_c%d_u%d_%lldx%lldx%lld", st->dim, st->is_complex ? 1 : 0, p->u_s,
+                (long long)st->n[0], (long long)st->n[1], (long long)st->n[2]);
+  return buf;
+}
+
+void load_tune_file() {
+  const char* f = std::getenv("GADI_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "r");
+  if (!fp) return;
+  char key[128];
+  int ry, L;
+  while (std::fscanf(fp, "%127s %d %d", key, &ry, &L) == 3) g_tune_cache[key] = {ry, L};
+  std::fclose(fp);
+}
+
+void save_tune_entry(const std::string& key, int ry, int L) {
+  const char* f = std::getenv("GADI_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s %d %d\n", key.c_str(), ry, L);
+  std::fclose(fp);
+}
+
+// Time CG iterations on H for one tile shape; returns microseconds per iteration.
+gadi_status time_shape(const gadi_stencil* st, const gadi_params* base, int ry, int L, hipStream_t stream, void* ws,
+                       size_t ws_bytes, const void* b, void* x, double* us_per_it) {
+  gadi_params q = *base;
+  q.tile_ry = ry;
+  q.tile_chunk = L;
+  q.normA = 1.0;
+  q.max_outer = 1;
+  q.fixed_inner_h = 1 << 30;
+  q.max_inner_h = 1 << 30;
+  q.tol = 0.0;
+  q.stag_window = 0;
+  q.div_factor = 0.0;
+  size_t need = 0;
+  gadi_status s = gadi_workspace_bytes(st, &q, &need);
+  if (s != GADI_OK) return s;
+  if (need > ws_bytes) return fail(GADI_ERR_WORKSPACE, "autotune workspace too small");
+  gadi_handle* h = nullptr;
+  s = gadi_create(st, &q, stream, ws, ws_bytes, &h);
+  if (s != GADI_OK) return s;
+  const int warm = 8, meas = 40;
+  s = start_solve(h, b, x);
+  if (s == GADI_OK) s = launch_steps(h, 2 + warm);           // IMPORT, OUTER, warm-up CG steps
+  hipEvent_t e0 = h->ev0, e1 = h->ev1;
+  if (s == GADI_OK && hipEventRecord(e0, stream) != hipSuccess) s = fail(GADI_ERR_HIP, "event");
+  if (s == GADI_OK) s = launch_steps(h, 2 * meas);
+  if (s == GADI_OK && hipEventRecord(e1, stream) != hipSuccess) s = fail(GADI_ERR_HIP, "event");
+  if (s == GADI_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(GADI_ERR_HIP, "event sync");
+  if (s == GADI_OK) s = read_ctl(h);
+  if (s == GADI_OK && !(h->h_ctl->phase == PH_H1 || h->h_ctl->phase == PH_H2))
+    s = fail(GADI_ERR_STATE, "autotune: state machine left the CG phase");
+  float ms = 0.f;
+  if (s == GADI_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+  h->running = 0;
+  gadi_destroy(h);
+  if (s != GADI_OK) return s;
+  *us_per_it = 1000.0 * ms / meas;
+  return GADI_OK;
+}
+
+}  // namespace
+
+extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* p, void* hip_stream, void* d_workspace,
+                                     size_t ws_bytes, const void* d_b, void* d_x, int32_t* ry, int32_t* chunk,
+                                     double* best_us) {
+  if (!ry || !chunk || !d_b || !d_x) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  gadi_status s = validate(st, p);
+  if (s != GADI_OK) return s;
+  const std::string key = tune_key(st, p);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune_cache.empty()) load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *ry = it->second.first;
+      *chunk = it->second.second;
+      if (best_us) *best_us = -1.0;
+      return GADI_OK;
+    }
+  }
+  std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
+  std::vector<int> Ls = st->dim == 3 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{2, 4, 8, 16, 32, 64};
+  double best = 1e300;
+  int bry = 0, bL = 0;
+  for (int r : rys)
+    for (int L : Ls) {
+      double us = 0.0;
+      s = time_shape(st, p, r, L, static_cast<hipStream_t>(hip_stream), d_workspace, ws_bytes, d_b, d_x, &us);
+      if (s != GADI_OK) return s;
+      if (us < best) { best = us; bry = r; bL = L; }
+    }
+  *ry = bry;
+  *chunk = bL;
+  if (best_us) *best_us = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = {bry, bL};
+  save_tune_entry(key, bry, bL);
+  return GADI_OK;
+}

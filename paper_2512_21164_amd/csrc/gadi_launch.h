@@ -1,0 +1,17 @@
+// Host-callable launchers of the gfx950 kernels (defined in gadi_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gadi_internal.h"
+
+namespace gadi {
+
+// One device step for every system of `tab` (all of class us/cplx/dim/ry).
+hipError_t launch_step(int us, int cplx, int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
+hipError_t launch_set_phase(GadiCtl* c, int phase, int norm_iters, double norm_scale, hipStream_t st);
+hipError_t launch_set_io(GadiDesc* d, const double* b, double* x, hipStream_t st);
+hipError_t launch_set_norm(GadiCtl* c, double normA, hipStream_t st);
+hipError_t launch_apply_dense(int cplx, int dim, int nx, int ny, int nz, double cA, const double* lo, const double* hi,
+                              double shift, int transpose, const double* x, double* y, hipStream_t st);
+
+}  // namespace gadi

@@ -1,0 +1,8 @@
+// Step-kernel instantiations for u_s element type cx<bf16>.
+#include "gadi_step.inc"
+
+namespace gadi {
+hipError_t launch_step_cbf16(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
+  return launch_step_dim<cx<bf16>>(dim, ry, tab, grid, st);
+}
+}  // namespace gadi

@@ -1,0 +1,8 @@
+// Step-kernel instantiations for u_s element type double.
+#include "gadi_step.inc"
+
+namespace gadi {
+hipError_t launch_step_f64(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
+  return launch_step_dim<double>(dim, ry, tab, grid, st);
+}
+}  // namespace gadi
