@@ -887,6 +887,8 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
       double us = 0.0;
       s = time_shape(st, p, r, L, static_cast<hipStream_t>(hip_stream), d_workspace, ws_bytes, d_b, d_x, &us);
       if (s != GADI_OK) return s;
+      if (std::getenv("GADI_TUNE_VERBOSE"))
+        std::fprintf(stderr, "gadi_autotune %s ry=%d chunk=%d: %.2f us per CG iteration\n", key.c_str(), r, L, us);
       if (us < best) { best = us; bry = r; bL = L; }
     }
   *ry = bry;
