@@ -116,6 +116,8 @@ typedef struct {
   double normA;         /* ||A||_2 used in the backward error                        */
   double normb;
   double ms;            /* device time of the solve (hipEvent), milliseconds         */
+  double kernel_ms;     /* hipEvent time of the step launches alone, i.e. the solve
+                           without the host polls between launch chunks              */
   int32_t status;       /* GADI_OK .. GADI_DIVERGED                                   */
   int32_t steps;        /* device steps launched (including idle steps at the end)   */
 } gadi_report;

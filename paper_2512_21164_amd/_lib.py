@@ -42,7 +42,8 @@ class gadi_params(C.Structure):
 class gadi_report(C.Structure):
     _fields_ = [("outer", C.c_int64), ("inner_h", C.c_int64), ("inner_s", C.c_int64),
                 ("be", C.c_double), ("relres", C.c_double), ("normA", C.c_double),
-                ("normb", C.c_double), ("ms", C.c_double), ("status", C.c_int32),
+                ("normb", C.c_double), ("ms", C.c_double), ("kernel_ms", C.c_double),
+                ("status", C.c_int32),
                 ("steps", C.c_int32)]
 
     def as_dict(self):

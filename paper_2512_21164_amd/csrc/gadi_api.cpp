@@ -241,6 +241,8 @@ struct gadi_handle {
   GadiCtl* h_ctl;        // pinned readback buffer
   double normA;
   hipEvent_t ev0, ev1;
+  hipEvent_t ec0, ec1;   // around each chunk of step launches
+  double kernel_ms;
   // asynchronous solve
   int running;
   int chunk;
@@ -277,10 +279,14 @@ int64_t step_bound(const gadi_params& p, int cplx) {
 
 gadi_status run_to(gadi_handle* h, int target_phase, bool wait, int64_t bound) {
   for (;;) {
+    HIP_TRY(hipEventRecord(h->ec0, h->stream));
     gadi_status s = launch_steps(h, h->chunk);
     if (s != GADI_OK) return s;
+    HIP_TRY(hipEventRecord(h->ec1, h->stream));
     s = read_ctl(h);
     if (s != GADI_OK) return s;
+    float cms = 0.f;
+    if (hipEventElapsedTime(&cms, h->ec0, h->ec1) == hipSuccess) h->kernel_ms += cms;
     if (h->h_ctl->phase == target_phase) return GADI_OK;
     if (h->steps > bound) return fail(GADI_ERR_STATE, "device state machine did not finish within its step bound");
     h->chunk = std::min(h->chunk * 2, 256);
@@ -301,6 +307,7 @@ void fill_report(gadi_handle* h, gadi_report* out) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) ms = -1.f;
   out->ms = ms;
+  out->kernel_ms = h->kernel_ms;
   out->status = c.status;
   out->steps = (int32_t)std::min<int64_t>(h->steps, INT32_MAX);
 }
@@ -319,6 +326,7 @@ gadi_status start_solve(gadi_handle* h, const void* b, void* x) {
   HIP_TRY(launch_set_io(h->d_desc, static_cast<const double*>(b), static_cast<double*>(x), h->stream));
   HIP_TRY(launch_set_phase(h->d_ctl, PH_IMPORT, 0, 0.0, h->stream));
   h->steps = 0;
+  h->kernel_ms = 0.0;
   h->chunk = 16;
   h->max_steps = step_bound(h->p, h->lay.cplx);
   h->running = 1;
@@ -418,7 +426,8 @@ gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_
     h->h_ctl = nullptr;
     return cleanup(fail(GADI_ERR_HIP, "pinned host buffer"));
   }
-  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipEventCreate(&h->ec0) != hipSuccess || hipEventCreate(&h->ec1) != hipSuccess)
     return cleanup(fail(GADI_ERR_HIP, "event create"));
   // single-system table: desc pointer and tile prefix live right after the table header
   char* tb = h->ws + l.o_table;
@@ -525,6 +534,8 @@ gadi_status gadi_destroy(gadi_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   (void)hipEventDestroy(h->ev0);
   (void)hipEventDestroy(h->ev1);
+  (void)hipEventDestroy(h->ec0);
+  (void)hipEventDestroy(h->ec1);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   delete h;
   return GADI_OK;
@@ -549,15 +560,20 @@ gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x
 }  // extern "C"
 
 // ============================================================== batches
+// A batch keeps one device table per kernel class (u_s, complex, dimension,
+// rows per wave).  Each step launch of a class uses a persistent grid that
+// walks the tiles of all members of the class, so membership changes only
+// rewrite the tables; the captured hipGraph is rebuilt only when the set of
+// classes (or the number of steps per launch) changes.
 namespace {
 
 struct ClassGroup {
+  int key;
   int us, cplx, dim, ry;
-  std::vector<int> slots;     // member slots in this class (sorted)
+  int nsys;
   BatchTable* d_table;        // device table header
   GadiDesc** d_desc;          // device array of descriptor pointers
   int32_t* d_start;           // device prefix sums
-  int total_tiles;
 };
 
 }  // namespace
@@ -569,7 +585,8 @@ struct gadi_batch {
   size_t ws_bytes;
   std::vector<gadi_handle*> member;   // by slot (nullptr = free)
   std::vector<int> done;              // by slot
-  std::vector<ClassGroup> groups;     // one per kernel class, up to 8
+  std::vector<ClassGroup> groups;     // classes present, in key order
+  std::vector<int> graph_keys;        // classes captured in the graph
   bool dirty;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -580,7 +597,7 @@ struct gadi_batch {
 namespace {
 
 constexpr int kMaxGroups = 8;
-constexpr int kGroupGrid = 2048;     // persistent grid of a batch step launch
+constexpr int kGroupGrid = 2048;     // persistent grid of a batch step launch (multiple of 8)
 
 size_t group_bytes(int max_sys) {
   return align_up(sizeof(BatchTable)) + align_up(sizeof(GadiDesc*) * (size_t)max_sys) +
@@ -588,18 +605,18 @@ size_t group_bytes(int max_sys) {
 }
 
 gadi_status rebuild_tables(gadi_batch* b) {
-  // group active members by kernel class and upload per-class tables
   std::map<int, std::vector<int>> by;
   for (int i = 0; i < b->max_sys; ++i)
     if (b->member[i] && !b->done[i]) by[kernel_class_key(b->member[i]->lay)].push_back(i);
   if ((int)by.size() > kMaxGroups) return fail(GADI_ERR_CAPACITY, "too many kernel classes in one batch");
-  b->groups.clear();
+  std::vector<ClassGroup> groups;
   int gi = 0;
   for (auto& kv : by) {
     ClassGroup g{};
     const Layout& l0 = b->member[kv.second[0]]->lay;
+    g.key = kv.first;
     g.us = l0.us; g.cplx = l0.cplx; g.dim = l0.dim; g.ry = l0.RY;
-    g.slots = kv.second;
+    g.nsys = (int)kv.second.size();
     char* base = b->ws + gi * group_bytes(b->max_sys);
     g.d_table = reinterpret_cast<BatchTable*>(base);
     g.d_desc = reinterpret_cast<GadiDesc**>(base + align_up(sizeof(BatchTable)));
@@ -607,40 +624,39 @@ gadi_status rebuild_tables(gadi_batch* b) {
                                            align_up(sizeof(GadiDesc*) * (size_t)b->max_sys));
     std::vector<GadiDesc*> descs;
     std::vector<int32_t> start{0};
-    for (int s : g.slots) {
+    for (int s : kv.second) {
       descs.push_back(b->member[s]->d_desc);
       start.push_back(start.back() + b->member[s]->lay.max_tiles);
     }
-    g.total_tiles = start.back();
     BatchTable t{};
-    t.nsys = (int)g.slots.size();
-    t.total_tiles = g.total_tiles;
-    t.slots = (g.total_tiles + 7) / 8 * 8;
+    t.nsys = g.nsys;
+    t.total_tiles = start.back();
+    t.slots = (t.total_tiles + 7) / 8 * 8;
     t.desc = g.d_desc;
     t.tile_start = g.d_start;
-    HIP_TRY(hipMemcpyAsync(g.d_table, &t, sizeof(t), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(g.d_desc, descs.data(), descs.size() * sizeof(GadiDesc*), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(g.d_start, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
-    b->groups.push_back(g);
+    HIP_TRY(hipMemcpyAsync(g.d_table, &t, sizeof(t), hipMemcpyHostToDevice, b->stream));
+    // the host vectors are pageable: let the copies consume them before they go out of scope
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    groups.push_back(g);
     ++gi;
   }
-  // pageable sources: make sure the copies have consumed them
-  HIP_TRY(hipStreamSynchronize(b->stream));
+  std::vector<int> keys;
+  for (auto& g : groups) keys.push_back(g.key);
+  if (keys != b->graph_keys) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  }
+  b->groups = groups;
   b->dirty = false;
-  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return GADI_OK;
-}
-
-int group_grid(const ClassGroup& g) {
-  const int slots = (g.total_tiles + 7) / 8 * 8;
-  return std::min(slots, kGroupGrid);
 }
 
 gadi_status launch_groups(gadi_batch* b, int nsteps) {
   for (int s = 0; s < nsteps; ++s)
     for (auto& g : b->groups) {
-      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, g.d_table, group_grid(g), b->stream);
+      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, g.d_table, kGroupGrid, b->stream);
       if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("batch step: ") + hipGetErrorString(e));
     }
   return GADI_OK;
@@ -685,12 +701,14 @@ gadi_status gadi_batch_create(int32_t max_systems, void* hip_stream, void* d_wor
 
 gadi_status gadi_batch_add(gadi_batch* b, gadi_handle* h, const void* d_b, void* d_x, int32_t* slot) {
   if (!b || !h || !d_b || !d_x) return fail(GADI_ERR_INVALID_ARG, "null argument");
-  if (h->stream != b->stream) return fail(GADI_ERR_INVALID_ARG, "handle and batch use different streams");
   if (h->running || h->in_batch) return fail(GADI_ERR_STATE, "handle busy");
   int free_slot = -1;
   for (int i = 0; i < b->max_sys; ++i)
     if (!b->member[i]) { free_slot = i; break; }
   if (free_slot < 0) return fail(GADI_ERR_CAPACITY, "batch full");
+  // the handle was created (and synchronized) on its own stream; from now on
+  // it is driven on the batch's stream
+  h->stream = b->stream;
   gadi_status s = start_solve(h, d_b, d_x);
   if (s != GADI_OK) return s;
   h->running = 0;          // progress is driven by the batch
@@ -709,21 +727,28 @@ gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps) {
     if (s != GADI_OK) return s;
   }
   if (b->groups.empty() || nsteps == 0) return GADI_OK;
-  // capture a graph of `nsteps` steps once per membership and relaunch it
-  if (!b->exec || b->graph_steps != nsteps) {
-    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  if (b->stream == nullptr) {
+    // the legacy default stream cannot be captured: launch directly
     gadi_status s = launch_groups(b, nsteps);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(b->stream, &g);
-    if (s != GADI_OK) { if (g) (void)hipGraphDestroy(g); return s; }
-    if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
-    b->graph = g;
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    b->graph_steps = nsteps;
+    if (s != GADI_OK) return s;
+  } else {
+    if (!b->exec || b->graph_steps != nsteps) {
+      if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+      if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+      HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      gadi_status s = launch_groups(b, nsteps);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (s != GADI_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+      if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
+      b->graph = g;
+      HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_steps = nsteps;
+      b->graph_keys.clear();
+      for (auto& gr : b->groups) b->graph_keys.push_back(gr.key);
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   }
-  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   for (int i = 0; i < b->max_sys; ++i)
     if (b->member[i] && !b->done[i]) b->member[i]->steps += nsteps;
   return GADI_OK;

@@ -1,0 +1,160 @@
+"""Continuous-batching request loop for GADI solves on one GPU.
+
+Requests (a convection-diffusion system each) arrive over time.  The loop
+admits a waiting request when a batch slot is free and its HBM footprint
+(workspace + b + x) fits in the remaining budget, creates its solver on a
+side stream (so the norm estimate and right-hand side overlap the running
+batch), and adds it to the batch, whose members keep their Krylov state
+resident until they finish.  Between step launches finished members are
+retired and their memory is released.  The loop reports per-request latency
+(arrival to result), p50 / p99, and solves per second over the makespan.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List
+
+import numpy as np
+
+from .api import Problem, Solver, apply, make_params, workspace_bytes
+from .batch import Batch
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival_s: float
+    admitted_s: float
+    finished_s: float
+    status: str
+    outer: int
+    inner_h: int
+    inner_s: int
+    be: float
+    forward_error: float
+    n: int
+    footprint: int
+
+    @property
+    def latency_s(self) -> float:
+        return self.finished_s - self.arrival_s
+
+
+def request_problem(req) -> Problem:
+    return Problem.convection_diffusion(req.dim, req.side, req.beta)
+
+
+class Server:
+    """Admission by HBM footprint + continuous batching over the C-ABI batch."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, u_s: str = "f64", tol: float = 1e-10,
+                 max_outer: int = 20000, norm_iters: int = 30, steps_per_launch: int = 16, device="cuda",
+                 keep_solutions: bool = False):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.params = dict(u_s=u_s, tol=tol, max_outer=max_outer, norm_iters=norm_iters, omega=1.0)
+        self.U = int(steps_per_launch)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.side = torch.cuda.Stream(device=self.device)
+        self.batch = Batch(self.max_slots, stream=self.stream, device=self.device)
+        self.keep = keep_solutions
+        self.solutions: Dict[int, np.ndarray] = {}
+        self.max_used = 0
+
+    def footprint(self, req) -> int:
+        pr = request_problem(req)
+        p = make_params(alpha=req.alpha, **self.params)
+        return workspace_bytes(pr, p) + 3 * 8 * pr.size     # workspace + b, x, x_true
+
+    def _start(self, req):
+        import workloads
+        torch = self.torch
+        pr = request_problem(req)
+        with torch.cuda.stream(self.side):
+            xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).to(self.device, non_blocking=False)
+            b = apply(pr, xt, stream=self.side)
+            x = torch.zeros_like(b)
+            s = Solver(pr, stream=self.side, device=self.device, alpha=req.alpha, **self.params)
+        self.side.synchronize()
+        return s, b, x, xt
+
+    def run(self, trace, time_scale: float = 1.0, log=None) -> List[Result]:
+        """Serve the requests of ``trace`` (arrival times scaled by time_scale)."""
+        torch = self.torch
+        pending = collections.deque(sorted(trace, key=lambda r: r.arrival_s))
+        waiting = collections.deque()
+        active = {}
+        used = 0
+        results: List[Result] = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while pending or waiting or active:
+            t = now()
+            while pending and pending[0].arrival_s * time_scale <= t:
+                waiting.append(pending.popleft())
+            while waiting and len(active) < self.max_slots:
+                req = waiting[0]
+                fp = self.footprint(req)
+                if fp > self.budget:
+                    waiting.popleft()
+                    results.append(Result(req.rid, req.arrival_s * time_scale, now(), now(), "REJECTED", 0, 0, 0,
+                                          float("nan"), float("nan"), req.n, fp))
+                    continue
+                if used + fp > self.budget:
+                    break
+                waiting.popleft()
+                s, b, x, xt = self._start(req)
+                slot = self.batch.add(s, b, x)
+                used += fp
+                self.max_used = max(self.max_used, used)
+                active[slot] = (req, now(), fp, xt)
+            if active:
+                self.batch.step(self.U)
+                done, _ = self.batch.poll()
+                for slot in done:
+                    s, b, x, rep = self.batch.remove(slot)
+                    req, t_adm, fp, xt = active.pop(slot)
+                    fe = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
+                    if self.keep:
+                        self.solutions[req.rid] = x.cpu().numpy()
+                    results.append(Result(req.rid, req.arrival_s * time_scale, t_adm, now(), rep["status_name"],
+                                          rep["outer"], rep["inner_h"], rep["inner_s"], rep["be"], fe, req.n, fp))
+                    s.close()
+                    del s, b, x, xt
+                    used -= fp
+                    if log:
+                        log(results[-1])
+            elif pending:
+                time.sleep(max(0.0, min(0.002, pending[0].arrival_s * time_scale - now())))
+        return results
+
+    def close(self):
+        self.batch.close()
+
+
+def summarize(results: List[Result]) -> dict:
+    done = [r for r in results if r.status != "REJECTED"]
+    lat = np.array([r.latency_s for r in done]) if done else np.array([np.nan])
+    first = min(r.arrival_s for r in results)
+    last = max(r.finished_s for r in results)
+    return {
+        "requests": len(results),
+        "completed": len(done),
+        "converged": sum(r.status == "OK" for r in done),
+        "not_converged": sum(r.status != "OK" for r in done),
+        "rejected": sum(r.status == "REJECTED" for r in results),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(np.mean(lat)),
+        "makespan_s": last - first,
+        "solves_per_s": len(done) / max(last - first, 1e-9),
+        "max_backward_error_converged": float(max([r.be for r in done if r.status == "OK"], default=np.nan)),
+    }
+
+
+__all__ = ["Server", "Result", "summarize", "request_problem"]

@@ -1,0 +1,114 @@
+"""Batched execution and the serving loop (GPU).
+
+A member of a batch computes exactly what it computes alone: its tiles, its
+reduction order and its state machine do not depend on the other members,
+so solutions are compared bitwise.  The serving loop must keep admitted
+footprints within the HBM budget, finish every request, and return the same
+solutions as solo solves.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import gadi_ref, problems
+from tests._problems import gpu_problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MIX = [  # (dim, side, beta, alpha, u_s)
+    (2, 40, 10.0, 0.3, "f64"),
+    (2, 96, 30.0, 0.05, "bf16"),
+    (3, 12, 5.0, 0.2, "f64"),
+    (2, 33, 0.0, 0.5, "f32"),
+    (3, 17, 20.0, 0.1, "bf16"),
+    (2, 130, 5.0, 0.02, "f32"),
+]
+
+
+def _case(dim, side, beta, alpha, us, seed):
+    import torch
+    from paper_2512_21164_amd import Solver
+    spec = problems.convection_diffusion(dim, side, (beta,) * dim)
+    A = problems.assemble(spec)
+    xt = workloads.x_true(spec.size, seed)
+    b = A @ xt
+    nA = gadi_ref.norm2(A)
+    s = Solver(gpu_problem(spec), normA=nA, alpha=alpha, u_s=us, tol=1e-10, max_outer=5000)
+    bd = to_dev(b)
+    return s, bd, torch.zeros_like(bd), (A, b, nA)
+
+
+def test_batch_members_equal_solo_runs(gpu_lib):
+    from paper_2512_21164_amd.batch import Batch
+    solo = []
+    for i, c in enumerate(MIX):
+        s, bd, xd, _ = _case(*c, seed=i)
+        x, rep = s.solve(bd, xd)
+        solo.append((x.cpu().numpy(), rep))
+        s.close()
+    batch = Batch(16)
+    keep = {}
+    for i, c in enumerate(MIX):
+        s, bd, xd, sysinfo = _case(*c, seed=i)
+        slot = batch.add(s, bd, xd)
+        keep[slot] = (i, s, bd, xd, sysinfo)
+    reps = batch.run(steps_per_launch=24)
+    assert len(reps) == len(MIX)
+    for slot, rep in reps.items():
+        i, s, bd, xd, (A, b, nA) = keep[slot]
+        xs, rs = solo[i]
+        assert rep["status"] == 0 and rs["status"] == 0
+        assert rep["outer"] == rs["outer"] and rep["inner_h"] == rs["inner_h"] and rep["inner_s"] == rs["inner_s"]
+        xb = xd.cpu().numpy()
+        assert np.array_equal(xb, xs), MIX[i]
+        assert gadi_ref.backward_error(A, xb, b, nA, extended=True) <= 1.01e-10
+        s.close()
+    batch.close()
+
+
+def test_batch_add_while_running(gpu_lib):
+    """Members admitted while others are on the device finish with solo results."""
+    from paper_2512_21164_amd.batch import Batch
+    batch = Batch(8)
+    first = [_case(*MIX[i], seed=10 + i) for i in range(3)]
+    slots = {batch.add(s, bd, xd): (i, s, bd, xd) for i, (s, bd, xd, _) in enumerate(first)}
+    batch.step(40)
+    late = [_case(*MIX[i], seed=10 + i) for i in range(3, 6)]
+    for j, (s, bd, xd, _) in enumerate(late):
+        slots[batch.add(s, bd, xd)] = (3 + j, s, bd, xd)
+    reps = batch.run(steps_per_launch=16)
+    for slot, rep in reps.items():
+        i, s, bd, xd = slots[slot]
+        s2, bd2, xd2, _ = _case(*MIX[i], seed=10 + i)
+        x2, r2 = s2.solve(bd2, xd2)
+        assert np.array_equal(xd.cpu().numpy(), x2.cpu().numpy())
+        s.close()
+        s2.close()
+    batch.close()
+
+
+def test_serving_loop_budget_and_solo_equality(gpu_lib):
+    import torch
+    from paper_2512_21164_amd import Problem, Solver, apply
+    from paper_2512_21164_amd.serve import Server, request_problem, summarize
+    trace = workloads.scale_trace(workloads.poisson_trace(num=20, rate_per_s=400.0, seed=3), 80, 20)
+    trace = [t for t in trace]
+    srv = Server(budget_bytes=0, max_slots=8, u_s="bf16", max_outer=3000, keep_solutions=True)
+    fps = [srv.footprint(r) for r in trace]
+    srv.budget = int(2.5 * max(fps))          # admission binds: only a few fit at once
+    res = srv.run(trace)
+    summ = summarize(res)
+    assert summ["completed"] == len(trace)
+    assert srv.max_used <= srv.budget
+    assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+    for r in res[:5]:
+        req = next(q for q in trace if q.rid == r.rid)
+        pr = request_problem(req)
+        xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).cuda()
+        b = apply(pr, xt)
+        s = Solver(pr, alpha=req.alpha, u_s="bf16", tol=1e-10, max_outer=3000, norm_iters=30)
+        x, rep = s.solve(b, torch.zeros_like(b))
+        s.close()
+        assert rep["status_name"] == r.status
+        assert np.array_equal(x.cpu().numpy(), srv.solutions[r.rid])
+    srv.close()
