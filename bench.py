@@ -142,13 +142,18 @@ def main():
         x = torch.zeros_like(b)
         for _ in range(warmup):
             x.zero_()
-            s.solve(b, x)
+            _, wrep = s.solve(b, x)
+            print(f"[bench] {us} warm-up solve: {wrep['status_name']} outer={wrep['outer']} ms={wrep['ms']:.1f}",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
+        for i in range(steps):
             x.zero_()
             x, rep, hist = s.solve(b, x, history=True)
             reps.append((rep, hist))
+            print(f"[bench] {us} solve {i + 1}/{steps}: {rep['status_name']} outer={rep['outer']} "
+                  f"inner_h={rep['inner_h']} inner_s={rep['inner_s']} be={rep['be']:.3e} ms={rep['ms']:.1f}",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         fe = float(torch.linalg.norm(x - xt) / nxt)

@@ -118,6 +118,28 @@ gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
   return GADI_OK;
 }
 
+// Waves of one kernel class resident on the whole device (with a fallback
+// when no device is visible, e.g. for workspace sizing on a build host).
+int64_t resident_waves(int us, int cplx, int dim, int ry) {
+  static std::mutex mu;
+  static std::map<int, int64_t> cache;
+  const int key = ((us * 2 + cplx) * 4 + dim) * 8 + ry;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0;
+  int64_t waves = 256 * 4 * 4;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+    const int nb = step_blocks_per_cu(us, cplx, dim, ry);
+    if (nb > 0) waves = (int64_t)cus * nb * 4;
+  } else {
+    (void)hipGetLastError();
+  }
+  cache[key] = waves;
+  return waves;
+}
+
 int default_ry(int us, int cplx) {
   if (cplx) return 1;
   return us == US_F64 ? 2 : (us == US_F32 ? 2 : 1);
@@ -137,15 +159,19 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
     l.RY = p->tile_ry ? p->tile_ry : default_ry(l.us, l.cplx);
   }
   l.nwy = (l.dim == 2) ? 1 : (l.ny_plane + l.RY - 1) / l.RY;
-  const int vi = 16 / us_bytes(l.us, l.cplx);
+  // elements per lane of the inner phases (16-byte lane accesses; 8 bytes for BF16)
+  const int vi = l.cplx ? (l.us == US_F64 ? 1 : (l.us == US_F32 ? 2 : 4)) : (l.us == US_F64 ? 2 : 4);
   if (p->tile_chunk > 0) {
     l.L = p->tile_chunk;
   } else {
-    // about 8192 wave tiles (32 per CU) for large grids, 4..64 planes each
+    // One full round of resident waves: (CUs x resident blocks x 4) wave
+    // tiles of the inner phases, so that no launch ends with a partial round.
     const int64_t nwx = (l.nx + 64 * vi - 1) / (64 * vi);
     const int64_t per_plane = nwx * l.nwy;
-    int64_t L = (per_plane * l.nm + 8191) / 8192;
-    L = std::max<int64_t>(4, std::min<int64_t>(64, L));
+    const int64_t waves = resident_waves(l.us, l.cplx, l.dim, l.RY);
+    const int64_t chunks = std::max<int64_t>(1, waves / std::max<int64_t>(1, per_plane));
+    int64_t L = (l.nm + chunks - 1) / chunks;
+    L = std::max<int64_t>(4, std::min<int64_t>(256, L));
     l.L = (int)L;
   }
   l.nmc = (l.nm + l.L - 1) / l.L;
@@ -904,10 +930,17 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
     }
   }
   std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
-  std::vector<int> Ls = st->dim == 3 ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{2, 4, 8, 16, 32, 64};
   double best = 1e300;
   int bry = 0, bL = 0;
-  for (int r : rys)
+  for (int r : rys) {
+    // candidates: the one-round chunk of this shape, its half and double, and fixed lengths
+    gadi_params q = *p;
+    q.tile_ry = r;
+    q.tile_chunk = 0;
+    const int Ldef = make_layout(st, &q).L;
+    std::vector<int> Ls{std::max(2, Ldef / 2), Ldef, 2 * Ldef, 8, 16, 32, 64};
+    std::sort(Ls.begin(), Ls.end());
+    Ls.erase(std::unique(Ls.begin(), Ls.end()), Ls.end());
     for (int L : Ls) {
       double us = 0.0;
       s = time_shape(st, p, r, L, static_cast<hipStream_t>(hip_stream), d_workspace, ws_bytes, d_b, d_x, &us);
@@ -916,6 +949,7 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
         std::fprintf(stderr, "gadi_autotune %s ry=%d chunk=%d: %.2f us per CG iteration\n", key.c_str(), r, L, us);
       if (us < best) { best = us; bry = r; bL = L; }
     }
+  }
   *ry = bry;
   *chunk = bL;
   if (best_us) *best_us = best;

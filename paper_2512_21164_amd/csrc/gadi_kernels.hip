@@ -10,6 +10,30 @@ hipError_t launch_step_c128(int dim, int ry, const BatchTable* tab, int grid, hi
 hipError_t launch_step_c64(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
 hipError_t launch_step_cbf16(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
 
+int occupancy_f64(int dim, int ry);
+int occupancy_f32(int dim, int ry);
+int occupancy_bf16(int dim, int ry);
+int occupancy_c128(int dim, int ry);
+int occupancy_c64(int dim, int ry);
+int occupancy_cbf16(int dim, int ry);
+
+int step_blocks_per_cu(int us, int cplx, int dim, int ry) {
+  if (!cplx) {
+    switch (us) {
+      case US_F64: return occupancy_f64(dim, ry);
+      case US_F32: return occupancy_f32(dim, ry);
+      case US_BF16: return occupancy_bf16(dim, ry);
+    }
+  } else {
+    switch (us) {
+      case US_F64: return occupancy_c128(dim, ry);
+      case US_F32: return occupancy_c64(dim, ry);
+      case US_BF16: return occupancy_cbf16(dim, ry);
+    }
+  }
+  return 0;
+}
+
 hipError_t launch_step(int us, int cplx, int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
   if (!cplx) {
     switch (us) {
