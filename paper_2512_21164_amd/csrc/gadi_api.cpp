@@ -140,10 +140,7 @@ int64_t resident_waves(int us, int cplx, int dim, int ry) {
   return waves;
 }
 
-int default_ry(int us, int cplx) {
-  if (cplx) return 1;
-  return us == US_F64 ? 2 : (us == US_F32 ? 2 : 1);
-}
+int default_ry(int, int) { return 1; }
 
 Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   Layout l{};
@@ -929,7 +926,7 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
       return GADI_OK;
     }
   }
-  std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
+  std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2} : std::vector<int>{1};
   double best = 1e300;
   int bry = 0, bL = 0;
   for (int r : rys) {

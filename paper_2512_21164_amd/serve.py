@@ -158,3 +158,49 @@ def summarize(results: List[Result]) -> dict:
 
 
 __all__ = ["Server", "Result", "summarize", "request_problem"]
+
+
+def main(argv=None):
+    """Serve a Poisson trace of convection-diffusion requests; print a JSON summary per precision."""
+    import argparse
+    import json
+    import sys
+
+    import workloads
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-side2d", type=int, default=1024)
+    ap.add_argument("--max-side3d", type=int, default=128)
+    ap.add_argument("--budget-gb", type=float, default=2.0, help="HBM admission budget")
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--max-outer", type=int, default=20000)
+    ap.add_argument("--steps-per-launch", type=int, default=16)
+    ap.add_argument("--us", default="bf16,f64", help="comma-separated inner precisions to run, in order")
+    args = ap.parse_args(argv)
+    trace = workloads.scale_trace(workloads.poisson_trace(args.requests, args.rate, args.seed),
+                                  args.max_side2d, args.max_side3d)
+    out = {}
+    for us in args.us.split(","):
+        srv = Server(int(args.budget_gb * 2 ** 30), max_slots=args.slots, u_s=us, max_outer=args.max_outer,
+                     steps_per_launch=args.steps_per_launch)
+        done = [0]
+
+        def log(r, us=us):
+            done[0] += 1
+            if done[0] % 16 == 0 or done[0] == len(trace):
+                print(f"[serve {us}] {done[0]}/{len(trace)} done, last: rid={r.rid} n={r.n} {r.status} "
+                      f"outer={r.outer} latency={r.latency_s:.3f}s", file=sys.stderr, flush=True)
+        res = srv.run(trace, log=log)
+        summ = summarize(res)
+        summ["max_admitted_bytes"] = srv.max_used
+        summ["budget_bytes"] = srv.budget
+        out[us] = summ
+        srv.close()
+    print(json.dumps({"serving": out, "requests": args.requests, "rate_per_s": args.rate,
+                      "max_side2d": args.max_side2d, "max_side3d": args.max_side3d, "max_outer": args.max_outer}))
+
+
+if __name__ == "__main__":
+    main()
