@@ -181,7 +181,7 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   size_t o = 0;
   l.o_desc = o; o = align_up(o + sizeof(GadiDesc));
   l.o_ctl = o; o = align_up(o + sizeof(GadiCtl));
-  l.o_counter = o; o = align_up(o + 64);
+  l.o_counter = o; o = align_up(o + GADI_TICKET_BYTES);
   l.o_table = o; o = align_up(o + sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t) + 64);
   l.o_partials = o; o = align_up(o + 4 * sizeof(double) * (size_t)l.max_tiles);
   l.o_hist = o; o = align_up(o + 4 * sizeof(double) * (size_t)l.hist_len);

@@ -7,7 +7,8 @@
 //              phase, iteration counters and the CG / CGNE scalars; only the
 //              last tile of a step writes it;
 //   partials   four doubles per tile for the reductions of a step;
-//   counter    tiles finished in the current step (last-tile detection);
+//   counters   two-level tickets of the tiles finished in the current step
+//              (last-tile detection);
 //   history    per sweep: BE, relres, CG and CGNE iteration counts;
 //   vectors    x^(k) (two FP64 buffers, ping-pong), padded b, and four
 //              u_s vectors shared by the two inner solves.
@@ -16,6 +17,11 @@
 // of a row is aligned; the padding stays zero.
 #pragma once
 #include <stdint.h>
+
+#define GADI_TICKET_GROUPS 64
+// bytes of the ticket counters of one system: a top counter and
+// GADI_TICKET_GROUPS group counters, 256 bytes apart
+#define GADI_TICKET_BYTES (256 * (1 + GADI_TICKET_GROUPS))
 
 namespace gadi {
 
@@ -96,7 +102,7 @@ struct GadiDesc {
   const double* user_b;
   double* user_x;
   double* partials;        // 4 doubles per tile
-  uint32_t* counter;
+  uint32_t* counter;       // top counter, followed by the group counters
   GadiCtl* ctl;
   double* hist;            // 4 doubles per sweep
 };
