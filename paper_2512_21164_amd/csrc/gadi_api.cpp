@@ -185,10 +185,14 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   l.o_table = o; o = align_up(o + sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t) + 64);
   l.o_partials = o; o = align_up(o + 4 * sizeof(double) * (size_t)l.max_tiles);
   l.o_hist = o; o = align_up(o + 4 * sizeof(double) * (size_t)l.hist_len);
-  l.o_x0 = o; o = align_up(o + l.welem * (size_t)l.nvec);
-  l.o_x1 = o; o = align_up(o + l.welem * (size_t)l.nvec);
-  l.o_b = o; o = align_up(o + l.welem * (size_t)l.nvec);
-  for (int i = 0; i < 4; ++i) { l.o_vs[i] = o; o = align_up(o + l.selem * (size_t)l.nvec); }
+  // The stencil sweeps load whole 64-lane rows, so a wave at the end of the
+  // last row reads up to one wave access (64 lanes x 16 bytes) past the
+  // vector: every vector is followed by that much slack.
+  const size_t tail = 64 * 16;
+  l.o_x0 = o; o = align_up(o + l.welem * (size_t)l.nvec + tail);
+  l.o_x1 = o; o = align_up(o + l.welem * (size_t)l.nvec + tail);
+  l.o_b = o; o = align_up(o + l.welem * (size_t)l.nvec + tail);
+  for (int i = 0; i < 4; ++i) { l.o_vs[i] = o; o = align_up(o + l.selem * (size_t)l.nvec + tail); }
   l.total = o;
   return l;
 }

@@ -1,0 +1,111 @@
+"""More GPU checks: precisions on 3D and complex problems, the autotuner, full-size sampling.
+
+Full-size checks use the grid of the headline workload (4096 x 4096) in the
+launch configuration the benchmark uses: one GADI sweep with fixed inner
+iteration counts compared with the oracle (the oracle finishes one sweep in
+tens of seconds), and a complete mixed-precision solve whose backward error
+is recomputed by the oracle in extended precision.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import gadi_ref, problems
+from tests._problems import gpu_problem, oracle_system, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(spec, b, normA, x0=None, **kw):
+    import torch
+    from paper_2512_21164_amd import Solver
+    s = Solver(gpu_problem(spec), normA=normA, **kw)
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd) if x0 is None else to_dev(x0)
+    x, rep = s.solve(bd, xd)
+    s.close()
+    return x.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_3d_mixed_precision_reaches_1e10(gpu_lib, prec):
+    spec, A, x, b = oracle_system(3, 20, (10.0, 10.0, 10.0), seed=2, dist="normal")
+    nA = gadi_ref.norm2(A)
+    xg, rep = _solve(spec, b, nA, alpha=0.3, u_s=prec, tol=1e-10, max_outer=5000)
+    assert rep["status"] == 0
+    assert gadi_ref.backward_error(A, xg, b, nA, extended=True) <= 1.01e-10
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_complex_mixed_precision_reaches_1e10(gpu_lib, prec):
+    spec = problems.complex_reaction_diffusion(40, 10.0)
+    A = problems.assemble(spec)
+    b = workloads.complex_rhs(spec.size, 5)
+    nA = gadi_ref.norm2(A)
+    xg, rep = _solve(spec, b, nA, alpha=0.2, u_s=prec, tol=1e-10, max_outer=5000)
+    assert rep["status"] == 0
+    assert gadi_ref.backward_error(A, xg, b, nA, extended=True) <= 1.01e-10
+    xd = np.linalg.solve(A.toarray(), b)
+    assert gadi_ref.forward_error(xg, xd) <= 1e-6
+
+
+def test_complex_fp64_solution_matches_dense(gpu_lib):
+    spec = problems.complex_reaction_diffusion(24, 1000.0)
+    A = problems.assemble(spec)
+    b = workloads.complex_rhs(spec.size, 6)
+    nA = gadi_ref.norm2(A)
+    ref = gadi_ref.gadi(A, b, 0.3, 1.0, normA=nA, tol=1e-12, max_outer=5000)
+    xg, rep = _solve(spec, b, nA, alpha=0.3, tol=1e-12, max_outer=5000)
+    assert rep["status"] == 0 and rep["outer"] == ref.outer
+    assert rel(xg, ref.x) <= 1e-12
+
+
+def test_autotune_returns_a_valid_shape(gpu_lib):
+    import torch
+    from paper_2512_21164_amd import Problem, apply, autotune, Solver
+    pr = Problem.convection_diffusion(3, 40, 10.0)
+    xt = torch.from_numpy(workloads.x_true(pr.size, 0)).cuda()
+    b = apply(pr, xt)
+    x = torch.zeros_like(b)
+    ry, ch, us = autotune(pr, b, x, alpha=0.1, u_s="f32")
+    assert ry in (1, 2) and ch >= 2 and us > 0
+    assert float(torch.linalg.norm(x)) == 0.0          # x is not written
+    s = Solver(pr, alpha=0.1, u_s="f32", tile_ry=ry, tile_chunk=ch, tol=1e-10, max_outer=3000)
+    x, rep = s.solve(b, x)
+    s.close()
+    assert rep["status"] == 0
+
+
+@pytest.mark.slow
+def test_full_size_one_sweep_parity(gpu_lib):
+    """C2 grid (4096^2): one sweep, 3 CG + 2 CGNE iterations, FP64, against the oracle."""
+    spec, A, x, b = oracle_system(2, 4096, (10.0, 10.0), seed=0)
+    nA = 8.0
+    ref = gadi_ref.gadi(A, b, 0.3728, 1.0, normA=nA, max_outer=1, tol=0.0, stag_window=0, div_factor=0.0,
+                        rule_h=gadi_ref.InnerRule(fixed=3), rule_s=gadi_ref.InnerRule(fixed=2))
+    xg, rep = _solve(spec, b, nA, alpha=0.3728, max_outer=1, tol=0.0, stag_window=0, div_factor=0.0,
+                     fixed_inner_h=3, fixed_inner_s=2)
+    assert rel(xg, ref.x) <= 1e-12
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, spec.size, 4096)
+    assert np.max(np.abs(xg[idx] - ref.x[idx])) <= 1e-12 * np.max(np.abs(ref.x))
+
+
+@pytest.mark.slow
+def test_full_size_mixed_solve_backward_error(gpu_lib):
+    """C2 grid, BF16-stored inner solves: the oracle recomputes the BE of the returned x."""
+    import torch
+    from paper_2512_21164_amd import Problem, Solver, apply
+    pr = Problem.convection_diffusion(2, 4096, 10.0)
+    xt = workloads.x_true(pr.size, 0)
+    b = apply(pr, torch.from_numpy(xt).cuda())
+    s = Solver(pr, alpha=1.0, u_s="bf16", tol=1e-10, max_outer=6000)
+    x, rep = s.solve(b, torch.zeros_like(b))
+    normA = s.normA
+    s.close()
+    assert rep["status"] == 0
+    spec = problems.convection_diffusion(2, 4096, (10.0, 10.0))
+    A = problems.assemble(spec)
+    bh = b.cpu().numpy()
+    be = gadi_ref.backward_error(A, x.cpu().numpy(), bh, normA)
+    assert be <= 1.01e-10
