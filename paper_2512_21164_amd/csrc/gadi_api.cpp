@@ -51,7 +51,7 @@ struct Layout {
   int dim, cplx, us;
   int nx, ny, nz;
   int64_t P, nvec, n;
-  int ny_plane, nm, RY, L, nwy, nmc;
+  int ny_plane, nm, RY, L, Lo, nwy;
   int64_t sy, sm;
   Tiling ti, to;
   int max_tiles;
@@ -66,11 +66,13 @@ int us_bytes(int us, int cplx) {
   return cplx ? 2 * b : b;
 }
 
-Tiling make_tiling(const Layout& l, int V) {
-  Tiling t;
+Tiling make_tiling(const Layout& l, int V, int L) {
+  Tiling t{};
   t.V = V;
+  t.L = L;
+  t.nmc = (l.nm + L - 1) / L;
   t.nwx = (int)((l.nx + 64 * V - 1) / (64 * V));
-  int64_t nwave = (int64_t)t.nwx * l.nwy * l.nmc;
+  int64_t nwave = (int64_t)t.nwx * l.nwy * t.nmc;
   t.nwave = (int)nwave;
   t.ntiles = (int)((nwave + 3) / 4);
   return t;
@@ -156,24 +158,25 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
     l.RY = p->tile_ry ? p->tile_ry : default_ry(l.us, l.cplx);
   }
   l.nwy = (l.dim == 2) ? 1 : (l.ny_plane + l.RY - 1) / l.RY;
-  // elements per lane of the inner phases (16-byte lane accesses; 8 bytes for BF16)
-  const int vi = l.cplx ? (l.us == US_F64 ? 1 : (l.us == US_F32 ? 2 : 4)) : (l.us == US_F64 ? 2 : 4);
-  if (p->tile_chunk > 0) {
-    l.L = p->tile_chunk;
-  } else {
-    // One full round of resident waves: (CUs x resident blocks x 4) wave
-    // tiles of the inner phases, so that no launch ends with a partial round.
-    const int64_t nwx = (l.nx + 64 * vi - 1) / (64 * vi);
+  // elements per lane of the inner phases (16-byte lane accesses)
+  const int vi = l.cplx ? (l.us == US_F64 ? 1 : (l.us == US_F32 ? 2 : 4))
+                        : (l.us == US_F64 ? 2 : (l.us == US_F32 ? 4 : GADI_BF16_V));
+  // Chunk length of a tiling: one full round of resident waves (CUs x
+  // resident blocks x 4 wave tiles), so that no launch ends with a partial
+  // round.  tile_chunk overrides it for the inner tiling.
+  const int64_t waves = resident_waves(l.us, l.cplx, l.dim, l.RY);
+  auto one_round = [&](int V) -> int {
+    const int64_t nwx = (l.nx + 64 * V - 1) / (64 * V);
     const int64_t per_plane = nwx * l.nwy;
-    const int64_t waves = resident_waves(l.us, l.cplx, l.dim, l.RY);
     const int64_t chunks = std::max<int64_t>(1, waves / std::max<int64_t>(1, per_plane));
-    int64_t L = (l.nm + chunks - 1) / chunks;
-    L = std::max<int64_t>(4, std::min<int64_t>(256, L));
-    l.L = (int)L;
-  }
-  l.nmc = (l.nm + l.L - 1) / l.L;
-  l.ti = make_tiling(l, vi);
-  l.to = make_tiling(l, l.cplx ? 1 : 2);
+    const int64_t L = (l.nm + chunks - 1) / chunks;
+    return (int)std::max<int64_t>(4, std::min<int64_t>(256, L));
+  };
+  const int vo = l.cplx ? 1 : 2;
+  l.L = p->tile_chunk > 0 ? p->tile_chunk : one_round(vi);
+  l.Lo = one_round(vo);
+  l.ti = make_tiling(l, vi, l.L);
+  l.to = make_tiling(l, vo, l.Lo);
   l.max_tiles = std::max(l.ti.ntiles, l.to.ntiles);
   l.hist_len = std::min<int64_t>(p->max_outer + 1, kHistCap);
   l.welem = l.cplx ? 16 : 8;
@@ -200,9 +203,9 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
 void fill_desc(GadiDesc& d, const Layout& l, const gadi_stencil* st, const gadi_params* p, char* ws) {
   std::memset(&d, 0, sizeof(d));
   d.dim = l.dim; d.cplx = l.cplx; d.us = l.us; d.RY = l.RY;
-  d.nx = l.nx; d.ny = l.ny; d.nz = l.nz; d.L = l.L;
+  d.nx = l.nx; d.ny = l.ny; d.nz = l.nz;
   d.P = l.P; d.n = l.n; d.nvec = l.nvec;
-  d.ny_plane = l.ny_plane; d.nm = l.nm; d.nwy = l.nwy; d.nmc = l.nmc;
+  d.ny_plane = l.ny_plane; d.nm = l.nm; d.nwy = l.nwy;
   d.sy = l.sy; d.sm = l.sm;
   d.ti = l.ti; d.to = l.to; d.max_tiles = l.max_tiles;
   // kernel axis order: 0 = x, 1 = in-plane y (3D), 2 = marching axis (2D: y, 3D: z)
@@ -464,6 +467,8 @@ gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_
   t.slots = (l.max_tiles + 7) / 8 * 8;
   t.desc = reinterpret_cast<GadiDesc**>(tb + sizeof(BatchTable));
   t.tile_start = reinterpret_cast<int32_t*>(tb + sizeof(BatchTable) + sizeof(GadiDesc*));
+  t.one = h->d_desc;
+  t.one_ctl = h->d_ctl;
   std::vector<char> tbuf(sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t));
   std::memcpy(tbuf.data(), &t, sizeof(t));
   std::memcpy(tbuf.data() + sizeof(BatchTable), &h->d_desc, sizeof(GadiDesc*));
@@ -501,7 +506,8 @@ gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p) {
   if (s != GADI_OK) return s;
   if (p->u_s != h->p.u_s) return fail(GADI_ERR_INVALID_ARG, "u_s cannot change");
   Layout l = make_layout(&h->st, p);
-  if (l.total > h->ws_bytes || l.max_tiles != h->lay.max_tiles || l.RY != h->lay.RY || l.L != h->lay.L)
+  if (l.total > h->ws_bytes || l.max_tiles != h->lay.max_tiles || l.RY != h->lay.RY || l.L != h->lay.L ||
+      l.Lo != h->lay.Lo)
     return fail(GADI_ERR_INVALID_ARG, "new parameters change the workspace layout; create a new handle");
   GadiDesc d;
   fill_desc(d, l, &h->st, p, h->ws);
@@ -661,6 +667,10 @@ gadi_status rebuild_tables(gadi_batch* b) {
     t.slots = (t.total_tiles + 7) / 8 * 8;
     t.desc = g.d_desc;
     t.tile_start = g.d_start;
+    if (g.nsys == 1) {
+      t.one = b->member[kv.second[0]]->d_desc;
+      t.one_ctl = b->member[kv.second[0]]->d_ctl;
+    }
     HIP_TRY(hipMemcpyAsync(g.d_desc, descs.data(), descs.size() * sizeof(GadiDesc*), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(g.d_start, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(g.d_table, &t, sizeof(t), hipMemcpyHostToDevice, b->stream));

@@ -18,6 +18,12 @@
 #pragma once
 #include <stdint.h>
 
+// BF16 elements per lane in the inner phases of real problems (8-byte lane
+// accesses; 8 doubles them, at the cost of registers)
+#ifndef GADI_BF16_V
+#define GADI_BF16_V 4
+#endif
+
 #define GADI_TICKET_GROUPS 64
 // bytes of the ticket counters of one system: a top counter and
 // GADI_TICKET_GROUPS group counters, 256 bytes apart
@@ -61,24 +67,29 @@ struct GadiCtl {
   double pad1[3];
 };
 
-// Geometry of one tiling (elements per lane V; the rest is shared).
+// Geometry of one tiling: V elements per lane, chunks of L planes along the
+// marching axis (each tiling sized so that its wave tiles fill the device
+// once); the in-plane row grouping is shared.
 struct Tiling {
   int32_t V;
   int32_t nwx;        // wave tiles along x
   int32_t nwave;      // wave tiles in total
   int32_t ntiles;     // blocks of 4 waves
+  int32_t L;          // planes per chunk
+  int32_t nmc;        // chunks along the marching axis
+  int32_t pad0, pad1;
 };
 
 struct GadiDesc {
   // problem
   int32_t dim, cplx, us, RY;
-  int32_t nx, ny, nz, L;
+  int32_t nx, ny, nz, pad_n;
   int64_t P;           // padded row pitch (elements)
   int64_t n;           // nx * ny * nz
   int64_t nvec;        // elements per padded vector (P * ny * nz)
   // kernel geometry: axis 0 = x, axis 1 = in-plane y (3D only), axis 2 = marching
   int32_t ny_plane, nm;    // rows in a plane (3D: ny; 2D: 1), marching extent
-  int32_t nwy, nmc;        // row groups per plane, chunks along the marching axis
+  int32_t nwy, pad_g;      // row groups per plane
   int64_t sy, sm;          // strides (elements) of in-plane y and marching axes
   Tiling ti;               // inner phases: V = 16 bytes / sizeof(u_s element)
   Tiling to;               // FP64 phases: V = 16 bytes / sizeof(FP64 element)
@@ -115,6 +126,8 @@ struct BatchTable {
   int32_t pad;
   GadiDesc** desc;         // [nsys]
   int32_t* tile_start;     // [nsys + 1] prefix sums of max_tiles
+  GadiDesc* one;           // nsys == 1: the system's descriptor and control
+  GadiCtl* one_ctl;        // block (saves two dependent loads per launch)
 };
 
 }  // namespace gadi
