@@ -292,7 +292,8 @@ gadi_status read_ctl(gadi_handle* h) {
 gadi_status launch_steps(gadi_handle* h, int count) {
   const int grid = (h->lay.max_tiles + 7) / 8 * 8;
   for (int i = 0; i < count; ++i) {
-    hipError_t e = launch_step(h->lay.us, h->lay.cplx, h->lay.dim, h->lay.RY, h->d_table, grid, h->stream);
+    const StepArgs args{h->d_table, h->d_desc, h->d_ctl};
+    hipError_t e = launch_step(h->lay.us, h->lay.cplx, h->lay.dim, h->lay.RY, args, grid, h->stream);
     if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("step launch: ") + hipGetErrorString(e));
   }
   h->steps += count;
@@ -467,8 +468,6 @@ gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_
   t.slots = (l.max_tiles + 7) / 8 * 8;
   t.desc = reinterpret_cast<GadiDesc**>(tb + sizeof(BatchTable));
   t.tile_start = reinterpret_cast<int32_t*>(tb + sizeof(BatchTable) + sizeof(GadiDesc*));
-  t.one = h->d_desc;
-  t.one_ctl = h->d_ctl;
   std::vector<char> tbuf(sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t));
   std::memcpy(tbuf.data(), &t, sizeof(t));
   std::memcpy(tbuf.data() + sizeof(BatchTable), &h->d_desc, sizeof(GadiDesc*));
@@ -597,7 +596,8 @@ gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x
 // rows per wave).  Each step launch of a class uses a persistent grid that
 // walks the tiles of all members of the class, so membership changes only
 // rewrite the tables; the captured hipGraph is rebuilt only when the set of
-// classes (or the number of steps per launch) changes.
+// classes, a class of one system (its pointers are kernel arguments) or the
+// number of steps per launch changes.
 namespace {
 
 struct ClassGroup {
@@ -607,6 +607,8 @@ struct ClassGroup {
   BatchTable* d_table;        // device table header
   GadiDesc** d_desc;          // device array of descriptor pointers
   int32_t* d_start;           // device prefix sums
+  const GadiDesc* one = nullptr;  // a group of one system: its descriptor
+  const GadiCtl* one_ctl = nullptr;  // and control block (step kernel arguments)
 };
 
 }  // namespace
@@ -620,6 +622,7 @@ struct gadi_batch {
   std::vector<int> done;              // by slot
   std::vector<ClassGroup> groups;     // classes present, in key order
   std::vector<int> graph_keys;        // classes captured in the graph
+  std::vector<const void*> graph_args;  // single-system kernel arguments captured in the graph
   bool dirty;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -668,8 +671,8 @@ gadi_status rebuild_tables(gadi_batch* b) {
     t.desc = g.d_desc;
     t.tile_start = g.d_start;
     if (g.nsys == 1) {
-      t.one = b->member[kv.second[0]]->d_desc;
-      t.one_ctl = b->member[kv.second[0]]->d_ctl;
+      g.one = b->member[kv.second[0]]->d_desc;
+      g.one_ctl = b->member[kv.second[0]]->d_ctl;
     }
     HIP_TRY(hipMemcpyAsync(g.d_desc, descs.data(), descs.size() * sizeof(GadiDesc*), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(g.d_start, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
@@ -680,8 +683,14 @@ gadi_status rebuild_tables(gadi_batch* b) {
     ++gi;
   }
   std::vector<int> keys;
-  for (auto& g : groups) keys.push_back(g.key);
-  if (keys != b->graph_keys) {
+  std::vector<const void*> args;
+  for (auto& g : groups) {
+    keys.push_back(g.key);
+    args.push_back(g.one);
+    args.push_back(g.one_ctl);
+  }
+  // the graph holds the kernel arguments: rebuild it when they change too
+  if (keys != b->graph_keys || args != b->graph_args) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   }
@@ -693,7 +702,7 @@ gadi_status rebuild_tables(gadi_batch* b) {
 gadi_status launch_groups(gadi_batch* b, int nsteps) {
   for (int s = 0; s < nsteps; ++s)
     for (auto& g : b->groups) {
-      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, g.d_table, kGroupGrid, b->stream);
+      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, StepArgs{g.d_table, g.one, g.one_ctl}, kGroupGrid, b->stream);
       if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("batch step: ") + hipGetErrorString(e));
     }
   return GADI_OK;
@@ -782,7 +791,12 @@ gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps) {
       HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
       b->graph_steps = nsteps;
       b->graph_keys.clear();
-      for (auto& gr : b->groups) b->graph_keys.push_back(gr.key);
+      b->graph_args.clear();
+      for (auto& gr : b->groups) {
+        b->graph_keys.push_back(gr.key);
+        b->graph_args.push_back(gr.one);
+        b->graph_args.push_back(gr.one_ctl);
+      }
     }
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   }

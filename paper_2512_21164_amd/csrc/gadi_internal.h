@@ -126,8 +126,15 @@ struct BatchTable {
   int32_t pad;
   GadiDesc** desc;         // [nsys]
   int32_t* tile_start;     // [nsys + 1] prefix sums of max_tiles
-  GadiDesc* one;           // nsys == 1: the system's descriptor and control
-  GadiCtl* one_ctl;        // block (saves two dependent loads per launch)
+};
+
+// Kernel argument of a step launch: the table, and for a table of one system
+// that system's descriptor and control block (null otherwise), which saves
+// the kernel two dependent loads before it knows its phase.
+struct StepArgs {
+  const BatchTable* tab;
+  const GadiDesc* one;
+  const GadiCtl* one_ctl;
 };
 
 }  // namespace gadi

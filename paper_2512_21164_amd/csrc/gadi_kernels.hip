@@ -3,12 +3,12 @@
 
 namespace gadi {
 
-hipError_t launch_step_f64(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
-hipError_t launch_step_f32(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
-hipError_t launch_step_bf16(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
-hipError_t launch_step_c128(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
-hipError_t launch_step_c64(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
-hipError_t launch_step_cbf16(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
+hipError_t launch_step_f64(int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
+hipError_t launch_step_f32(int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
+hipError_t launch_step_bf16(int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
+hipError_t launch_step_c128(int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
+hipError_t launch_step_c64(int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
+hipError_t launch_step_cbf16(int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
 
 int occupancy_f64(int dim, int ry);
 int occupancy_f32(int dim, int ry);
@@ -34,18 +34,18 @@ int step_blocks_per_cu(int us, int cplx, int dim, int ry) {
   return 0;
 }
 
-hipError_t launch_step(int us, int cplx, int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
+hipError_t launch_step(int us, int cplx, int dim, int ry, const StepArgs& args, int grid, hipStream_t st) {
   if (!cplx) {
     switch (us) {
-      case US_F64: return launch_step_f64(dim, ry, tab, grid, st);
-      case US_F32: return launch_step_f32(dim, ry, tab, grid, st);
-      case US_BF16: return launch_step_bf16(dim, ry, tab, grid, st);
+      case US_F64: return launch_step_f64(dim, ry, args, grid, st);
+      case US_F32: return launch_step_f32(dim, ry, args, grid, st);
+      case US_BF16: return launch_step_bf16(dim, ry, args, grid, st);
     }
   } else {
     switch (us) {
-      case US_F64: return launch_step_c128(dim, ry, tab, grid, st);
-      case US_F32: return launch_step_c64(dim, ry, tab, grid, st);
-      case US_BF16: return launch_step_cbf16(dim, ry, tab, grid, st);
+      case US_F64: return launch_step_c128(dim, ry, args, grid, st);
+      case US_F32: return launch_step_c64(dim, ry, args, grid, st);
+      case US_BF16: return launch_step_cbf16(dim, ry, args, grid, st);
     }
   }
   return hipErrorInvalidValue;

@@ -7,7 +7,7 @@
 namespace gadi {
 
 // One device step for every system of `tab` (all of class us/cplx/dim/ry).
-hipError_t launch_step(int us, int cplx, int dim, int ry, const BatchTable* tab, int grid, hipStream_t st);
+hipError_t launch_step(int us, int cplx, int dim, int ry, const StepArgs& args, int grid, hipStream_t st);
 // Resident 256-thread blocks per CU of the step kernel of this class (0 if unknown).
 int step_blocks_per_cu(int us, int cplx, int dim, int ry);
 hipError_t launch_set_phase(GadiCtl* c, int phase, int norm_iters, double norm_scale, hipStream_t st);

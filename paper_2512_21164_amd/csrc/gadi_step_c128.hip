@@ -2,8 +2,8 @@
 #include "gadi_step.inc"
 
 namespace gadi {
-hipError_t launch_step_c128(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
-  return launch_step_dim<cx<double>>(dim, ry, tab, grid, st);
+hipError_t launch_step_c128(int dim, int ry, const StepArgs& args, int grid, hipStream_t st) {
+  return launch_step_dim<cx<double>>(dim, ry, args, grid, st);
 }
 int occupancy_c128(int dim, int ry) { return occupancy_dim<cx<double>>(dim, ry); }
 }  // namespace gadi

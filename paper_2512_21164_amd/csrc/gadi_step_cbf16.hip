@@ -2,8 +2,8 @@
 #include "gadi_step.inc"
 
 namespace gadi {
-hipError_t launch_step_cbf16(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
-  return launch_step_dim<cx<bf16>>(dim, ry, tab, grid, st);
+hipError_t launch_step_cbf16(int dim, int ry, const StepArgs& args, int grid, hipStream_t st) {
+  return launch_step_dim<cx<bf16>>(dim, ry, args, grid, st);
 }
 int occupancy_cbf16(int dim, int ry) { return occupancy_dim<cx<bf16>>(dim, ry); }
 }  // namespace gadi

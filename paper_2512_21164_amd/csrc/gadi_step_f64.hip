@@ -2,8 +2,8 @@
 #include "gadi_step.inc"
 
 namespace gadi {
-hipError_t launch_step_f64(int dim, int ry, const BatchTable* tab, int grid, hipStream_t st) {
-  return launch_step_dim<double>(dim, ry, tab, grid, st);
+hipError_t launch_step_f64(int dim, int ry, const StepArgs& args, int grid, hipStream_t st) {
+  return launch_step_dim<double>(dim, ry, args, grid, st);
 }
 int occupancy_f64(int dim, int ry) { return occupancy_dim<double>(dim, ry); }
 }  // namespace gadi
