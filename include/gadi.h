@@ -103,7 +103,14 @@ typedef struct {
   int32_t norm_iters;      /* power iterations for the estimate (default 100)             */
   int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0: library default        */
   int32_t tile_chunk;      /* planes per tile along the marching axis; 0: default          */
-  int32_t reserved;
+  int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
+                              4.3, step 3); 0 (default): none                            */
+  double safeguard_tau;    /* > 0: before the solve, raise alpha until
+                              kappa(H) kappa(S) u_s < safeguard_tau (Section 4.3, step 2,
+                              eq. (239479)); 0 (default): no check.  Must exceed the unit
+                              roundoff of u_s (Table 1).                                  */
+  double alpha_growth;     /* factor of each alpha increase, > 1; default 10^(3/7), one
+                              step of eight log-spaced values per decade triple          */
 } gadi_params;
 
 /* Outcome of a solve. */
@@ -120,6 +127,9 @@ typedef struct {
                            without the host polls between launch chunks              */
   int32_t status;       /* GADI_OK .. GADI_DIVERGED                                   */
   int32_t steps;        /* device steps launched (including idle steps at the end)   */
+  double alpha;         /* alpha of the last attempt (after the safeguard / restarts) */
+  int32_t restarts;     /* alpha restarts performed                                  */
+  int32_t reserved;
 } gadi_report;
 
 typedef struct gadi_handle gadi_handle;
@@ -134,7 +144,8 @@ const char* gadi_last_error(void);
 
 /* Default parameters: alpha 0.5, omega 1, u_r = u = F64, u_s = F64, BE stop,
  * tol 1e-10, max_outer 20000, stag_window 200, inner_stag_window 20,
- * div_factor 1e3, inner tolerances 1e-3, caps 2000, normA estimated. */
+ * div_factor 1e3, inner tolerances 1e-3, caps 2000, normA estimated, no alpha
+ * safeguard or restarts (alpha_growth 10^(3/7)). */
 void gadi_params_default(gadi_params* p);
 
 /* Bytes of device workspace a handle needs for (stencil, params); 256-byte
@@ -150,6 +161,19 @@ gadi_status gadi_workspace_bytes(const gadi_stencil* st, const gadi_params* p, s
 gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_stream,
                         void* d_workspace, size_t ws_bytes, gadi_handle** out);
 
+/* Condition numbers of the two shifted splitting matrices for this stencil
+ * and alpha (host only, closed forms of the constant-coefficient stencils,
+ * Section 5 and the HSS splitting of Section 2.1):
+ *   kappa(H) = (alpha + lambda_max(M)) / (alpha + lambda_min(M)),
+ *   kappa(S) = sqrt(alpha^2 + rho(N)^2) / alpha  (an upper bound; exact when N
+ *              has a zero eigenvalue),
+ * with lambda(M) and rho(N) from the per-axis Toeplitz eigenvalues
+ * c/dim + 2 m_d cos(j pi/(n_d+1)), m_d = (lo_d+hi_d)/2, and
+ * i(shift_im + sum_d (hi_d-lo_d) cos(j_d pi/(n_d+1))).  Returns
+ * GADI_ERR_INVALID_ARG for a null pointer, an invalid stencil or alpha <= 0,
+ * and GADI_ERR_UNSUPPORTED when H is not positive definite for this alpha. */
+gadi_status gadi_condition_estimate(const gadi_stencil* st, double alpha, double* kappa_H, double* kappa_S);
+
 /* Change alpha / omega / tolerances of an existing handle (same operator and
  * precisions).  Must not be called while a solve is running. */
 gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p);
@@ -158,7 +182,16 @@ gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p);
  * reproduce Algorithm 1), out: the returned iterate.  out may be NULL.
  * h_history (nullable, host, length 4*(max_outer+1)) receives per sweep k:
  * [BE_k, relres_k, CG iterations of sweep k, CGNE iterations of sweep k].
- * Blocks until the solve is finished. */
+ * Blocks until the solve is finished.
+ *
+ * Alpha selection (Section 4.3): with safeguard_tau > 0 the solve starts from
+ * the smallest alpha * alpha_growth^m (m >= 0) with kappa(H) kappa(S) u_s <
+ * safeguard_tau (gadi_condition_estimate).  With max_restarts > 0, an attempt
+ * that ends STAGNATED or DIVERGED is followed by another with alpha multiplied
+ * by alpha_growth, starting from the last iterate after stagnation and from
+ * zero after divergence; all attempts share the max_outer budget.  The report
+ * sums sweeps and iterations over the attempts; h_history holds the last
+ * attempt. */
 gadi_status gadi_solve(gadi_handle* h, const void* d_b, void* d_x, gadi_report* out,
                        double* h_history);
 

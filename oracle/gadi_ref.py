@@ -35,6 +35,12 @@ The iteration returns x^(k) with status
                   value for stag_window sweeps,
     NOT_CONVERGED when k == max_outer,
 checked in that order.
+
+Alpha selection (Section 4.3): ``safeguarded_alpha`` raises alpha by a fixed
+factor until kappa(H) kappa(S) u_s < tau (closed-form condition numbers), and
+``gadi_select_alpha`` restarts with a larger alpha after an attempt that
+stagnated or diverged (from the last iterate, or from zero after divergence),
+all attempts sharing one sweep budget.
 """
 from __future__ import annotations
 
@@ -306,3 +312,73 @@ def gadi_two_step(A, b, alpha: float, omega: float, sweeps: int, x0=None):
         x = luS.solve((N - (1.0 - omega) * alpha * I) @ x + (2.0 - omega) * alpha * xh)
         out.append(x.copy())
     return out
+
+
+# --------------------------------------------------------------------------
+# Alpha selection and restarts (Section 4.3, steps 2 and 3)
+# --------------------------------------------------------------------------
+ALPHA_GROWTH = 10.0 ** (3.0 / 7.0)   # one step of eight log-spaced values of [1e-3, 1]
+
+
+def safeguarded_alpha(spec, alpha: float, prec: str, tau: float, growth: float = ALPHA_GROWTH) -> float:
+    """Step 2: the smallest alpha * growth^m (m >= 0) with kappa(H) kappa(S) u_s < tau.
+
+    kappa(H) and kappa(S) are the closed forms of ``closed_forms`` (exact for H;
+    for the normal S an upper bound, exact when N has a zero eigenvalue);
+    u_s is the unit roundoff of Table 1.  tau <= 0 disables the check.
+    """
+    from . import closed_forms
+    if tau <= 0.0:
+        return float(alpha)
+    u = lowprec.UNIT_ROUNDOFF[prec]
+    if not tau > u:
+        raise ValueError("tau must exceed the unit roundoff of u_s")
+    a = float(alpha)
+    for _ in range(4097):
+        if closed_forms.kappa_H(spec, a) * closed_forms.kappa_S(spec, a) * u < tau:
+            return a
+        a *= growth
+    raise ValueError("alpha safeguard cannot be met")
+
+
+@dataclasses.dataclass
+class RestartResult:
+    x: np.ndarray
+    status: int
+    outer: int              # sweeps over all attempts
+    inner_h: int            # CG iterations over all attempts
+    inner_s: int
+    alpha: float            # alpha of the last attempt
+    restarts: int
+    attempts: List[GadiResult]
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES[self.status]
+
+
+def gadi_select_alpha(A, b, alpha: float, omega: float, *, spec, normA: float, tau: float = 0.0,
+                      growth: float = ALPHA_GROWTH, max_restarts: int = 0, max_outer: int = 10000,
+                      prec: str = "f64", x0=None, **kw) -> RestartResult:
+    """Section 4.3: start from the safeguarded alpha (step 2); when an attempt ends
+    STAGNATED or DIVERGED, stop, multiply alpha by ``growth`` and run again (step 3)
+    from the last iterate (stagnation) or from zero (divergence), while restarts
+    and sweeps of the shared ``max_outer`` budget remain."""
+    a = safeguarded_alpha(spec, alpha, prec, tau, growth)
+    n = A.shape[0]
+    cplx = np.iscomplexobj(A.data) if hasattr(A, "data") else False
+    cplx = cplx or np.iscomplexobj(b)
+    wt = np.complex128 if cplx else np.float64
+    x = np.zeros(n, dtype=wt) if x0 is None else np.array(x0, dtype=wt)
+    used, restarts, attempts = 0, 0, []
+    while True:
+        res = gadi(A, b, a, omega, normA=normA, max_outer=max_outer - used, prec=prec, x0=x, **kw)
+        attempts.append(res)
+        used += res.outer
+        if res.status in (STAGNATED, DIVERGED) and restarts < max_restarts and used < max_outer:
+            x = res.x if res.status == STAGNATED else np.zeros(n, dtype=wt)
+            a *= growth
+            restarts += 1
+            continue
+        return RestartResult(res.x, res.status, used, sum(sum(t.inner_h) for t in attempts),
+                             sum(sum(t.inner_s) for t in attempts), a, restarts, attempts)

@@ -36,15 +36,16 @@ class gadi_params(C.Structure):
                 ("max_inner_h", C.c_int32), ("max_inner_s", C.c_int32),
                 ("fixed_inner_h", C.c_int32), ("fixed_inner_s", C.c_int32),
                 ("normA", C.c_double), ("norm_iters", C.c_int32),
-                ("tile_ry", C.c_int32), ("tile_chunk", C.c_int32), ("reserved", C.c_int32)]
+                ("tile_ry", C.c_int32), ("tile_chunk", C.c_int32), ("max_restarts", C.c_int32),
+                ("safeguard_tau", C.c_double), ("alpha_growth", C.c_double)]
 
 
 class gadi_report(C.Structure):
     _fields_ = [("outer", C.c_int64), ("inner_h", C.c_int64), ("inner_s", C.c_int64),
                 ("be", C.c_double), ("relres", C.c_double), ("normA", C.c_double),
                 ("normb", C.c_double), ("ms", C.c_double), ("kernel_ms", C.c_double),
-                ("status", C.c_int32),
-                ("steps", C.c_int32)]
+                ("status", C.c_int32), ("steps", C.c_int32),
+                ("alpha", C.c_double), ("restarts", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -66,6 +67,7 @@ SIGNATURES = [
     ("gadi_workspace_bytes", C.c_int32, [_S, _PP, C.POINTER(C.c_size_t)]),
     ("gadi_create", C.c_int32, [_S, _PP, _P, _P, C.c_size_t, C.POINTER(_P)]),
     ("gadi_set_params", C.c_int32, [_P, _PP]),
+    ("gadi_condition_estimate", C.c_int32, [_S, C.c_double, _D, _D]),
     ("gadi_solve", C.c_int32, [_P, _P, _P, _R, _D]),
     ("gadi_solve_async", C.c_int32, [_P, _P, _P]),
     ("gadi_query", C.c_int32, [_P, C.c_int32, _R, _D]),

@@ -78,8 +78,8 @@ Tiling make_tiling(const Layout& l, int V, int L) {
   return t;
 }
 
-gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
-  if (!st || !p) return fail(GADI_ERR_INVALID_ARG, "null stencil or params");
+gadi_status validate_stencil(const gadi_stencil* st) {
+  if (!st) return fail(GADI_ERR_INVALID_ARG, "null stencil");
   if (st->dim != 2 && st->dim != 3) return fail(GADI_ERR_INVALID_ARG, "dim must be 2 or 3");
   for (int d = 0; d < 3; ++d)
     if (st->n[d] < 1) return fail(GADI_ERR_INVALID_ARG, "grid sizes must be >= 1");
@@ -100,6 +100,22 @@ gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
   } else if (st->shift_im != 0.0) {
     return fail(GADI_ERR_INVALID_ARG, "shift_im needs is_complex = 1");
   }
+  return GADI_OK;
+}
+
+// Final statuses written by the device state machine (GADI_* values).
+constexpr int ST_STAGNATED_H = GADI_STAGNATED;
+constexpr int ST_DIVERGED_H = GADI_DIVERGED;
+
+// Unit roundoff of a storage precision (Table 1).
+double unit_roundoff(int us) {
+  return us == GADI_F64 ? std::ldexp(1.0, -53) : (us == GADI_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -8));
+}
+
+gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
+  if (!st || !p) return fail(GADI_ERR_INVALID_ARG, "null stencil or params");
+  gadi_status vs = validate_stencil(st);
+  if (vs != GADI_OK) return vs;
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(GADI_ERR_INVALID_ARG, "alpha must be > 0");
   if (!(p->omega >= 0.0 && p->omega < 2.0)) return fail(GADI_ERR_INVALID_ARG, "omega must lie in [0, 2)");
   if (p->u_r != GADI_F64 || p->u != GADI_F64)
@@ -117,6 +133,52 @@ gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
     return fail(GADI_ERR_INVALID_ARG, "tile_ry must be 0, 1, 2 or 4");
   if (p->tile_chunk < 0 || p->tile_chunk > 4096) return fail(GADI_ERR_INVALID_ARG, "tile_chunk out of range");
   if (!(p->div_factor >= 0.0)) return fail(GADI_ERR_INVALID_ARG, "div_factor must be >= 0");
+  if (p->max_restarts < 0 || p->max_restarts > 64) return fail(GADI_ERR_INVALID_ARG, "max_restarts must lie in [0, 64]");
+  if (!(p->alpha_growth > 1.0) || !std::isfinite(p->alpha_growth))
+    return fail(GADI_ERR_INVALID_ARG, "alpha_growth must be > 1");
+  if (!(p->safeguard_tau >= 0.0) || !std::isfinite(p->safeguard_tau))
+    return fail(GADI_ERR_INVALID_ARG, "safeguard_tau must be >= 0");
+  if (p->safeguard_tau > 0.0 && !(p->safeguard_tau > unit_roundoff(p->u_s)))
+    return fail(GADI_ERR_INVALID_ARG, "safeguard_tau must exceed the unit roundoff of u_s");
+  return GADI_OK;
+}
+
+// Closed-form condition numbers of H = alpha I + M and S = alpha I + N for the
+// constant-coefficient stencil (per-axis Toeplitz eigenvalues, Kronecker sums).
+gadi_status condition_estimate(const gadi_stencil* st, double alpha, double* kH, double* kS) {
+  const double pi = 3.14159265358979323846;
+  double lmin = 0.0, lmax = 0.0, rho = std::fabs(st->shift_im);
+  const double c = st->center / st->dim;
+  for (int d = 0; d < st->dim; ++d) {
+    const double cth = std::cos(pi / (double)(st->n[d] + 1));   // largest |cos(j pi/(n+1))|
+    const double m = 0.5 * (st->lo[d] + st->hi[d]);
+    const double nu = 0.5 * (st->hi[d] - st->lo[d]);
+    lmin += c - 2.0 * std::fabs(m) * cth;
+    lmax += c + 2.0 * std::fabs(m) * cth;
+    rho += 2.0 * std::fabs(nu) * cth;
+  }
+  if (!(alpha + lmin > 0.0)) return fail(GADI_ERR_UNSUPPORTED, "alpha I + M is not positive definite");
+  *kH = (alpha + lmax) / (alpha + lmin);
+  *kS = std::sqrt(alpha * alpha + rho * rho) / alpha;
+  return GADI_OK;
+}
+
+// Section 4.3, step 2: the smallest alpha * growth^m meeting kappa(H) kappa(S) u_s < tau.
+gadi_status safeguarded_alpha(const gadi_stencil* st, const gadi_params& p, double* alpha) {
+  double a = p.alpha;
+  if (p.safeguard_tau > 0.0) {
+    const double u = unit_roundoff(p.u_s);
+    for (int it = 0;; ++it) {
+      double kH = 0.0, kS = 0.0;
+      gadi_status s = condition_estimate(st, a, &kH, &kS);
+      if (s != GADI_OK) return s;
+      if (kH * kS * u < p.safeguard_tau) break;
+      if (it >= 4096 || !std::isfinite(a * p.alpha_growth))
+        return fail(GADI_ERR_INVALID_ARG, "alpha safeguard cannot be met");
+      a *= p.alpha_growth;
+    }
+  }
+  *alpha = a;
   return GADI_OK;
 }
 
@@ -279,6 +341,13 @@ struct gadi_handle {
   int64_t steps;
   int64_t max_steps;
   int in_batch;
+  // alpha selection of the running solve (Section 4.3)
+  double alpha_cur;
+  int restarts;
+  int64_t acc_outer, acc_inner_h, acc_inner_s, acc_steps;
+  double acc_kernel_ms;
+  void* x_user;
+  const void* b_user;
 };
 
 namespace {
@@ -328,9 +397,9 @@ gadi_status run_to(gadi_handle* h, int target_phase, bool wait, int64_t bound) {
 void fill_report(gadi_handle* h, gadi_report* out) {
   if (!out) return;
   const GadiCtl& c = *h->h_ctl;
-  out->outer = c.k;
-  out->inner_h = c.inner_h_total;
-  out->inner_s = c.inner_s_total;
+  out->outer = h->acc_outer + c.k;
+  out->inner_h = h->acc_inner_h + c.inner_h_total;
+  out->inner_s = h->acc_inner_s + c.inner_s_total;
   out->be = c.be;
   out->relres = c.relres;
   out->normA = c.normA;
@@ -340,7 +409,10 @@ void fill_report(gadi_handle* h, gadi_report* out) {
   out->ms = ms;
   out->kernel_ms = h->kernel_ms;
   out->status = c.status;
-  out->steps = (int32_t)std::min<int64_t>(h->steps, INT32_MAX);
+  out->steps = (int32_t)std::min<int64_t>(h->acc_steps + h->steps, INT32_MAX);
+  out->alpha = h->alpha_cur;
+  out->restarts = h->restarts;
+  out->reserved = 0;
 }
 
 gadi_status copy_history(gadi_handle* h, double* hist) {
@@ -350,17 +422,66 @@ gadi_status copy_history(gadi_handle* h, double* hist) {
   return GADI_OK;
 }
 
+// Arm one attempt of the solve: descriptor with this alpha and sweep budget,
+// the caller's b / x, the state machine at IMPORT.
+gadi_status arm_attempt(gadi_handle* h, double alpha, int64_t max_outer) {
+  gadi_params q = h->p;
+  q.alpha = alpha;
+  q.max_outer = max_outer;
+  fill_desc(h->hdesc, h->lay, &h->st, &q, h->ws);
+  HIP_TRY(hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(GadiDesc), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(launch_set_io(h->d_desc, static_cast<const double*>(h->b_user), static_cast<double*>(h->x_user), h->stream));
+  HIP_TRY(launch_set_phase(h->d_ctl, PH_IMPORT, 0, 0.0, h->stream));
+  h->steps = 0;
+  h->chunk = 16;
+  h->max_steps = step_bound(q, h->lay.cplx);
+  return GADI_OK;
+}
+
 gadi_status start_solve(gadi_handle* h, const void* b, void* x) {
   if (!b || !x) return fail(GADI_ERR_INVALID_ARG, "null b or x");
   if (h->running || h->in_batch) return fail(GADI_ERR_STATE, "a solve is already running on this handle");
-  HIP_TRY(hipEventRecord(h->ev0, h->stream));
-  HIP_TRY(launch_set_io(h->d_desc, static_cast<const double*>(b), static_cast<double*>(x), h->stream));
-  HIP_TRY(launch_set_phase(h->d_ctl, PH_IMPORT, 0, 0.0, h->stream));
-  h->steps = 0;
+  double alpha = h->p.alpha;
+  gadi_status s = safeguarded_alpha(&h->st, h->p, &alpha);
+  if (s != GADI_OK) return s;
+  h->b_user = b;
+  h->x_user = x;
+  h->alpha_cur = alpha;
+  h->restarts = 0;
+  h->acc_outer = h->acc_inner_h = h->acc_inner_s = h->acc_steps = 0;
   h->kernel_ms = 0.0;
-  h->chunk = 16;
-  h->max_steps = step_bound(h->p, h->lay.cplx);
+  HIP_TRY(hipEventRecord(h->ev0, h->stream));
+  s = arm_attempt(h, alpha, h->p.max_outer);
+  if (s != GADI_OK) return s;
   h->running = 1;
+  return GADI_OK;
+}
+
+// Section 4.3, step 3: after an attempt that stagnated or diverged, stop,
+// raise alpha and start again (from the last iterate after stagnation, from
+// zero after divergence) while restarts and sweeps remain.
+bool wants_restart(const gadi_handle* h) {
+  const GadiCtl& c = *h->h_ctl;
+  return (c.status == ST_STAGNATED_H || c.status == ST_DIVERGED_H) && h->restarts < h->p.max_restarts &&
+         h->acc_outer + c.k < h->p.max_outer;
+}
+
+gadi_status restart_solve(gadi_handle* h) {
+  const GadiCtl& c = *h->h_ctl;
+  const bool diverged = c.status == ST_DIVERGED_H;
+  h->acc_outer += c.k;
+  h->acc_inner_h += c.inner_h_total;
+  h->acc_inner_s += c.inner_s_total;
+  h->acc_steps += h->steps;
+  h->restarts += 1;
+  h->alpha_cur *= h->p.alpha_growth;
+  if (diverged) {
+    const size_t elem = h->lay.cplx ? 16 : 8;
+    HIP_TRY(hipMemsetAsync(h->x_user, 0, elem * (size_t)h->lay.n, h->stream));
+  }
+  gadi_status s = arm_attempt(h, h->alpha_cur, h->p.max_outer - h->acc_outer);
+  if (s != GADI_OK) return s;
+  h->h_ctl->phase = PH_IMPORT;   // host view until the next read of the control block
   return GADI_OK;
 }
 
@@ -418,6 +539,9 @@ void gadi_params_default(gadi_params* p) {
   p->fixed_inner_h = 0;
   p->fixed_inner_s = 0;
   p->normA = 0.0;
+  p->max_restarts = 0;
+  p->safeguard_tau = 0.0;
+  p->alpha_growth = std::pow(10.0, 3.0 / 7.0);
   p->norm_iters = 100;
   p->tile_ry = 0;
   p->tile_chunk = 0;
@@ -498,6 +622,14 @@ gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_
   return GADI_OK;
 }
 
+gadi_status gadi_condition_estimate(const gadi_stencil* st, double alpha, double* kappa_H, double* kappa_S) {
+  if (!kappa_H || !kappa_S) return fail(GADI_ERR_INVALID_ARG, "null output");
+  gadi_status s = validate_stencil(st);
+  if (s != GADI_OK) return s;
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(GADI_ERR_INVALID_ARG, "alpha must be > 0");
+  return condition_estimate(st, alpha, kappa_H, kappa_S);
+}
+
 gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p) {
   if (!h || !p) return fail(GADI_ERR_INVALID_ARG, "null handle or params");
   if (h->running || h->in_batch) return fail(GADI_ERR_STATE, "solve running");
@@ -530,8 +662,13 @@ gadi_status gadi_solve(gadi_handle* h, const void* d_b, void* d_x, gadi_report* 
   if (!h) return fail(GADI_ERR_INVALID_ARG, "null handle");
   gadi_status s = start_solve(h, d_b, d_x);
   if (s != GADI_OK) return s;
-  s = run_to(h, PH_DONE, true, h->max_steps);
-  if (s != GADI_OK) { h->running = 0; return s; }
+  for (;;) {
+    s = run_to(h, PH_DONE, true, h->max_steps);
+    if (s != GADI_OK) { h->running = 0; return s; }
+    if (!wants_restart(h)) break;
+    s = restart_solve(h);
+    if (s != GADI_OK) { h->running = 0; return s; }
+  }
   return finish_solve(h, out, h_history);
 }
 
@@ -547,9 +684,14 @@ gadi_status gadi_query(gadi_handle* h, int32_t wait, gadi_report* out, double* h
   if (!h->running) return fail(GADI_ERR_STATE, "no solve running");
   gadi_status s = read_ctl(h);
   if (s != GADI_OK) return s;
-  if (h->h_ctl->phase != PH_DONE) {
-    s = run_to(h, PH_DONE, wait != 0, h->max_steps);
-    if (s == GADI_RUNNING) return s;
+  for (;;) {
+    if (h->h_ctl->phase != PH_DONE) {
+      s = run_to(h, PH_DONE, wait != 0, h->max_steps);
+      if (s == GADI_RUNNING) return s;
+      if (s != GADI_OK) { h->running = 0; return s; }
+    }
+    if (!wants_restart(h)) break;
+    s = restart_solve(h);
     if (s != GADI_OK) { h->running = 0; return s; }
   }
   return finish_solve(h, out, h_history);

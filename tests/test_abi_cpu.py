@@ -35,6 +35,7 @@ def test_defaults_and_strings():
     p = api.make_params()
     assert p.alpha == 0.5 and p.omega == 1.0 and p.tol == 1e-10 and p.u_s == _lib.GADI_F64
     assert p.max_outer == 20000 and p.stag_window == 200 and p.inner_stag_window == 20
+    assert p.max_restarts == 0 and p.safeguard_tau == 0.0 and p.alpha_growth == pytest.approx(10 ** (3 / 7), rel=1e-15)
     assert lib.gadi_status_string(0) == b"OK"
     assert lib.gadi_status_string(-3) == b"ERR_WORKSPACE"
     assert lib.gadi_version().startswith(b"gadi")
@@ -55,7 +56,9 @@ def test_workspace_size_scales_with_precision():
 
 @pytest.mark.parametrize("bad", [dict(alpha=0.0), dict(alpha=-1.0), dict(omega=2.0), dict(omega=-0.1),
                                  dict(u_r=1), dict(u=2), dict(u_s=7), dict(max_inner_h=0),
-                                 dict(tile_ry=3), dict(tol=-1.0), dict(normA=-1.0)])
+                                 dict(tile_ry=3), dict(tol=-1.0), dict(normA=-1.0), dict(max_restarts=-1),
+                                 dict(alpha_growth=1.0), dict(u_s="bf16", safeguard_tau=1e-3),
+                                 dict(safeguard_tau=-1.0)])
 def test_argument_errors(bad):
     pr = api.Problem.convection_diffusion(2, 32, 1.0)
     with pytest.raises(_lib.GadiError):
