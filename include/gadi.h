@@ -129,7 +129,8 @@ typedef struct {
   int32_t steps;        /* device steps launched (including idle steps at the end)   */
   double alpha;         /* alpha of the last attempt (after the safeguard / restarts) */
   int32_t restarts;     /* alpha restarts performed                                  */
-  int32_t reserved;
+  int32_t attempt_outer; /* sweeps of the last attempt: h_history holds
+                            attempt_outer + 1 entries (outer + 1 without restarts)    */
 } gadi_report;
 
 typedef struct gadi_handle gadi_handle;

@@ -45,7 +45,7 @@ class gadi_report(C.Structure):
                 ("be", C.c_double), ("relres", C.c_double), ("normA", C.c_double),
                 ("normb", C.c_double), ("ms", C.c_double), ("kernel_ms", C.c_double),
                 ("status", C.c_int32), ("steps", C.c_int32),
-                ("alpha", C.c_double), ("restarts", C.c_int32), ("reserved", C.c_int32)]
+                ("alpha", C.c_double), ("restarts", C.c_int32), ("attempt_outer", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -153,7 +153,9 @@ class Solver:
         return buf, buf.ctypes.data_as(C.POINTER(C.c_double))
 
     def solve(self, b, x=None, history: bool = False):
-        """Solve A x = b; returns (x, report dict[, history array (k, 4)])."""
+        """Solve A x = b; returns (x, report dict[, history array (k, 4)]).
+
+        The history covers the last attempt when alpha restarts happened."""
         import torch
         if x is None:
             x = torch.zeros_like(b)
@@ -166,7 +168,7 @@ class Solver:
         out = rep.as_dict()
         out["status_name"] = self.lib.gadi_status_string(st).decode()
         if history:
-            k = int(rep.outer) + 1
+            k = int(rep.attempt_outer) + 1
             return x, out, buf[: 4 * k].reshape(k, 4)
         return x, out
 

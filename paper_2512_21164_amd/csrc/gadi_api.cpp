@@ -412,7 +412,7 @@ void fill_report(gadi_handle* h, gadi_report* out) {
   out->steps = (int32_t)std::min<int64_t>(h->acc_steps + h->steps, INT32_MAX);
   out->alpha = h->alpha_cur;
   out->restarts = h->restarts;
-  out->reserved = 0;
+  out->attempt_outer = c.k;
 }
 
 gadi_status copy_history(gadi_handle* h, double* hist) {

@@ -123,21 +123,44 @@ def test_condition_estimate_errors():
 # ---------------------------------------------------------------- GPU
 @pytest.mark.gpu
 def test_gpu_restarts_match_oracle(gpu_lib):
-    """FP64, 15^2: same restart sequence, alpha, sweep and iteration counts, x to 1e-12."""
+    """FP64 mirror mode with fixed inner counts, 15^2: three restarts; same sequence of attempts,
+    alpha, sweep and iteration counts as the oracle, x to 1e-12.  (Fixed inner counts keep every
+    decision of the run far from a tie: the stagnation tests clear the 1% rule by >= 1e-5.)"""
     import torch
     from paper_2512_21164_amd import Solver
     spec, A, x, b, nA = _stagnating_case()
     kw = dict(tol=1e-12, stag_window=5)
-    ref = gadi_ref.gadi_select_alpha(A, b, 1e-4, 1.0, spec=spec, normA=nA, max_outer=3000, max_restarts=12, **kw)
-    s = Solver(gpu_problem(spec), normA=nA, alpha=1e-4, omega=1.0, max_outer=3000, max_restarts=12, **kw)
+    ref = gadi_ref.gadi_select_alpha(A, b, 1e-3, 1.0, spec=spec, normA=nA, max_outer=4000, max_restarts=12,
+                                     rule_h=gadi_ref.InnerRule(fixed=6), rule_s=gadi_ref.InnerRule(fixed=3), **kw)
+    assert ref.restarts == 3
+    s = Solver(gpu_problem(spec), normA=nA, alpha=1e-3, omega=1.0, max_outer=4000, max_restarts=12,
+               fixed_inner_h=6, fixed_inner_s=3, **kw)
     bd = to_dev(b)
-    xd = torch.zeros_like(bd)
-    xg, rep = s.solve(bd, xd)
+    xg, rep, hist = s.solve(bd, torch.zeros_like(bd), history=True)
     s.close()
     assert rep["status"] == ref.status == gadi_ref.OK
     assert rep["restarts"] == ref.restarts and rep["alpha"] == pytest.approx(ref.alpha, rel=1e-14)
     assert rep["outer"] == ref.outer and rep["inner_h"] == ref.inner_h and rep["inner_s"] == ref.inner_s
+    last = ref.attempts[-1]
+    assert rep["attempt_outer"] == last.outer and len(hist) == last.outer + 1
+    assert np.max(np.abs(hist[:, 0] - np.array(last.be))) <= 1e-13
     assert rel(xg.cpu().numpy(), ref.x) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_gpu_adaptive_restarts_converge(gpu_lib):
+    """Adaptive inner solves: the restarted solve reaches the target where a single attempt stagnates."""
+    import torch
+    from paper_2512_21164_amd import Solver
+    spec, A, x, b, nA = _stagnating_case()
+    s = Solver(gpu_problem(spec), normA=nA, alpha=1e-4, omega=1.0, max_outer=3000, max_restarts=12,
+               tol=1e-12, stag_window=5)
+    bd = to_dev(b)
+    xg, rep = s.solve(bd, torch.zeros_like(bd))
+    s.close()
+    assert rep["status"] == gadi_ref.OK and rep["restarts"] >= 2 and rep["outer"] <= 3000
+    assert rep["alpha"] == pytest.approx(1e-4 * G ** rep["restarts"], rel=1e-14)
+    assert gadi_ref.backward_error(A, xg.cpu().numpy(), b, nA, extended=True) <= 1.01e-12
 
 
 @pytest.mark.gpu
