@@ -62,8 +62,16 @@ enum {
 };
 
 /* Precision of a stage of Algorithm 1 (u_r, u, u_s; Section 2.3, Table 1).
- * GADI_BF16 means BF16 storage with FP32 arithmetic (Section 5.1). */
-typedef enum { GADI_F64 = 0, GADI_F32 = 1, GADI_BF16 = 2 } gadi_prec;
+ * GADI_BF16 means BF16 storage with FP32 arithmetic (Section 5.1).
+ * GADI_F64X2 (u_r only) is the extra-precision residual u_r < u of Section
+ * 2.3: FP64 data, products and sums carried exactly as unevaluated pairs of
+ * FP64 numbers (FMA TwoProduct, TwoSum; the Dot2 scheme of Ogita, Rump and
+ * Oishi, 2005), so that r = b - A x is as accurate as if computed in twice
+ * the FP64 precision and rounded once to FP64:
+ *   |r_i - (b - A x)_i| <= 2^-53 |(b - A x)_i| + gamma_K^2 sum_j |a_ij x_j|,
+ * gamma_K = K 2^-53 / (1 - K 2^-53), K the terms of row i (6 to 9).  This
+ * removes the kappa(A) u_r term from the forward-error limit (Theorem 2). */
+typedef enum { GADI_F64 = 0, GADI_F32 = 1, GADI_BF16 = 2, GADI_F64X2 = 3 } gadi_prec;
 
 /* The operator A (matrix-free).  At interior grid point p:
  *   (A u)_p = center*u_p + sum_d ( lo[d]*u_{p-e_d} + hi[d]*u_{p+e_d} )
@@ -86,7 +94,8 @@ typedef struct {
 typedef struct {
   double alpha;            /* regularization, > 0 (Section 2.1)                          */
   double omega;            /* extrapolation, in [0, 2) (Section 2.1)                      */
-  int32_t u_r, u, u_s;     /* precisions; u_r and u must be GADI_F64                      */
+  int32_t u_r, u, u_s;     /* precisions; u = GADI_F64; u_r = GADI_F64 (default) or
+                              GADI_F64X2 (fixed at gadi_create: it selects the kernels)  */
   int32_t stop_on_relres;  /* 0: backward error (default); 1: ||r||/||r0||                */
   double tol;              /* outer target, e.g. 1e-10                                    */
   int64_t max_outer;       /* sweep cap -> GADI_NOT_CONVERGED                             */
@@ -216,6 +225,17 @@ gadi_status gadi_destroy(gadi_handle* h);
  * Asynchronous on the stream.  x and y must not overlap. */
 gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x, void* d_y,
                        int32_t transpose);
+
+/* r = b - A x on dense vectors: the residual step of Algorithm 1 (Section
+ * 2.3) in precision u_r = GADI_F64 (plain FP64 arithmetic) or GADI_F64X2 (the
+ * extra-precision arithmetic described at gadi_prec, identical to the
+ * solver's residual with params.u_r = GADI_F64X2).  b, x, r: float64
+ * (complex128 interleaved if st->is_complex) with n[0]*n[1]*n[2] elements,
+ * x-fastest, caller-owned device memory.  r must not overlap b or x.
+ * Asynchronous on the stream; GADI_ERR_INVALID_ARG for null pointers, an
+ * invalid grid, an unknown u_r or overlapping r. */
+gadi_status gadi_residual(const gadi_stencil* st, void* hip_stream, const void* d_b, const void* d_x, void* d_r,
+                          int32_t u_r);
 
 /* ---- batched execution ------------------------------------------------------
  * A batch advances many handles together: one device step launch per

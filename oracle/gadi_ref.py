@@ -6,7 +6,7 @@ Algorithm 1 of Section 2.3 (mixed-precision GADI), run step by step:
 
     x^(0) = 0
     repeat
-        r^(k) = b - A x^(k)                              (u_r = FP64)
+        r^(k) = b - A x^(k)                              (u_r = FP64, or exact)
         solve (alpha I + M) z^(k) = r^(k)                (u_s)
         solve (alpha I + N) y^(k) = (2 - omega) alpha z^(k)   (u_s)
         x^(k+1) = x^(k) + y^(k)                          (u = FP64)
@@ -36,6 +36,10 @@ The iteration returns x^(k) with status
     NOT_CONVERGED when k == max_outer,
 checked in that order.
 
+Residual precision u_r (Section 2.3): "f64" forms b - A x in float64; "exact"
+is the extra-precision residual taken to its limit, b - A x computed exactly
+and rounded once to float64 (``residual_exact``).
+
 Alpha selection (Section 4.3): ``safeguarded_alpha`` raises alpha by a fixed
 factor until kappa(H) kappa(S) u_s < tau (closed-form condition numbers), and
 ``gadi_select_alpha`` restarts with a larger alpha after an attempt that
@@ -45,6 +49,7 @@ all attempts sharing one sweep budget.
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import List, Optional
 
 import numpy as np
@@ -183,6 +188,61 @@ def backward_error(A, x, b, normA: float, extended: bool = False) -> float:
     return float(np.linalg.norm(r) / (normA * np.linalg.norm(x) + np.linalg.norm(b)))
 
 
+def _split(v):
+    """Veltkamp's splitting: v = hi + lo exactly, each half with at most 26
+    significant bits (float64, factor 2^27 + 1; no overflow for |v| < 1e300)."""
+    c = 134217729.0 * v
+    hi = c - (c - v)
+    return hi, v - hi
+
+
+def _exact_products(a, v):
+    """The four float64 products of the halves of a and v; they sum to a*v exactly
+    (26 x 26 bits fit the 53-bit significand; no underflow for the magnitudes
+    used here)."""
+    ah, al = _split(np.asarray(a, dtype=np.float64))
+    vh, vl = _split(np.asarray(v, dtype=np.float64))
+    return np.stack([ah * vh, ah * vl, al * vh, al * vl], axis=-1)
+
+
+def residual_exact(A, b, x) -> np.ndarray:
+    """r = b - A x computed exactly and rounded once to float64 per entry.
+
+    This is the residual in extra precision u_r (Section 2.3) in its limit
+    u_r -> 0.  Each product a_ij x_j is expanded into exact float64 pieces and
+    ``math.fsum`` (Shewchuk's exact summation) returns the correctly rounded
+    sum of b_i and the negated pieces.  Complex entries are expanded into their
+    real products.
+    """
+    A = sp.csr_matrix(A)
+    cplx = np.iscomplexobj(A.data) or np.iscomplexobj(x) or np.iscomplexobj(b)
+    n = A.shape[0]
+    xv = np.asarray(x)[A.indices]
+    ptr = A.indptr
+    if not cplx:
+        P = -_exact_products(A.data.real, xv.real)
+        bb = np.asarray(b, dtype=np.float64)
+        return np.array([math.fsum([bb[i], *P[ptr[i]:ptr[i + 1]].ravel()]) for i in range(n)])
+    a = A.data.astype(np.complex128)
+    xv = xv.astype(np.complex128)
+    # (a x).re = a.re x.re - a.im x.im,  (a x).im = a.re x.im + a.im x.re
+    Pre = np.concatenate([-_exact_products(a.real, xv.real), _exact_products(a.imag, xv.imag)], axis=1)
+    Pim = np.concatenate([-_exact_products(a.real, xv.imag), -_exact_products(a.imag, xv.real)], axis=1)
+    bb = np.asarray(b, dtype=np.complex128)
+    re = [math.fsum([bb[i].real, *Pre[ptr[i]:ptr[i + 1]].ravel()]) for i in range(n)]
+    im = [math.fsum([bb[i].imag, *Pim[ptr[i]:ptr[i + 1]].ravel()]) for i in range(n)]
+    return np.array(re) + 1j * np.array(im)
+
+
+def residual(A, b, x, u_r: str = "f64") -> np.ndarray:
+    """The residual step of Algorithm 1 in precision u_r: "f64" or "exact"."""
+    if u_r == "f64":
+        return b - A @ x
+    if u_r == "exact":
+        return residual_exact(A, b, x)
+    raise ValueError("u_r must be 'f64' or 'exact'")
+
+
 def forward_error(x, x_ref) -> float:
     """||x - x_ref|| / ||x_ref|| (Section 3)."""
     return float(np.linalg.norm(np.asarray(x) - np.asarray(x_ref)) / np.linalg.norm(x_ref))
@@ -217,8 +277,10 @@ def gadi(A, b, alpha: float, omega: float, *, normA: float, tol: float = 1e-10,
          stop: str = "be", max_outer: int = 10000, inner: str = "mirror",
          prec: str = "f64", rule_h: Optional[InnerRule] = None,
          rule_s: Optional[InnerRule] = None, x0=None, stag_window: int = 200,
-         div_factor: float = 1e3, record_iterates: bool = False) -> GadiResult:
+         div_factor: float = 1e3, record_iterates: bool = False, u_r: str = "f64") -> GadiResult:
     """Run Algorithm 1 (Section 2.3) on A x = b with the HSS splitting.
+
+    u_r = "f64" or "exact" selects the precision of the residual step.
 
     inner = "mirror": CG on H and Craig CGNE on S in precision ``prec``.
     inner = "exact":  direct sparse LU solves of H and S (float64/complex128).
@@ -250,7 +312,7 @@ def gadi(A, b, alpha: float, omega: float, *, normA: float, tol: float = 1e-10,
         while True:
             if record_iterates:
                 res.iterates.append(x.copy())
-            r = b - A @ x                                    # residual in u_r = FP64
+            r = residual(A, b, x, u_r)                       # residual in u_r
             nr = float(np.linalg.norm(r))
             be = nr / (normA * float(np.linalg.norm(x)) + normb)
             if nr0 is None:

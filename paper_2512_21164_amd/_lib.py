@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libgadi.so")
 GADI_OK, GADI_NOT_CONVERGED, GADI_STAGNATED, GADI_DIVERGED, GADI_RUNNING = 0, 1, 2, 3, 4
 GADI_ERR_INVALID_ARG, GADI_ERR_UNSUPPORTED, GADI_ERR_WORKSPACE = -1, -2, -3
 GADI_ERR_HIP, GADI_ERR_CAPACITY, GADI_ERR_STATE = -4, -5, -6
-GADI_F64, GADI_F32, GADI_BF16 = 0, 1, 2
-PREC = {"f64": GADI_F64, "f32": GADI_F32, "bf16": GADI_BF16}
+GADI_F64, GADI_F32, GADI_BF16, GADI_F64X2 = 0, 1, 2, 3
+PREC = {"f64": GADI_F64, "f32": GADI_F32, "bf16": GADI_BF16, "f64x2": GADI_F64X2}
 
 
 class gadi_stencil(C.Structure):
@@ -74,6 +74,7 @@ SIGNATURES = [
     ("gadi_get_norm", C.c_int32, [_P, _D]),
     ("gadi_destroy", C.c_int32, [_P]),
     ("gadi_apply", C.c_int32, [_S, _P, _P, _P, C.c_int32]),
+    ("gadi_residual", C.c_int32, [_S, _P, _P, _P, _P, C.c_int32]),
     ("gadi_batch_workspace_bytes", C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
     ("gadi_batch_create", C.c_int32, [C.c_int32, _P, _P, C.c_size_t, C.POINTER(_P)]),
     ("gadi_batch_add", C.c_int32, [_P, _P, _P, _P, _I]),

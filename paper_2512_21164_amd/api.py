@@ -77,13 +77,14 @@ class Problem:
 def make_params(**kw) -> _lib.gadi_params:
     """gadi_params from keyword arguments over the library defaults.
 
-    u_s may be given as "f64", "f32", "bf16" or a GADI_* constant.
+    u_s and u_r may be given as "f64", "f32", "bf16", "f64x2" or a GADI_*
+    constant.
     """
     lib = _lib.load()
     p = _lib.gadi_params()
     lib.gadi_params_default(C.byref(p))
     for k, v in kw.items():
-        if k == "u_s" and isinstance(v, str):
+        if k in ("u_s", "u_r", "u") and isinstance(v, str):
             v = PREC[v]
         if not hasattr(p, k):
             raise KeyError(f"unknown parameter {k}")
@@ -203,15 +204,36 @@ class Solver:
             pass
 
 
+def _check_dense(problem: Problem, *vs):
+    """Every vector a dense utility kernel touches must hold the whole grid."""
+    for v in vs:
+        if not v.is_cuda or v.dtype != _dtype(problem) or not v.is_contiguous() or v.numel() != problem.size:
+            raise ValueError(f"expected a contiguous {_dtype(problem)} CUDA tensor of {problem.size} values")
+
+
 def apply(problem: Problem, x, transpose: bool = False, stream=None):
     """y = A x (or A^H x) on the device."""
     import torch
     lib = _lib.load()
+    _check_dense(problem, x)
     y = torch.empty_like(x)
     _lib.check(lib.gadi_apply(C.byref(problem.c_struct()), C.c_void_p(_stream_handle(stream)),
                               C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), 1 if transpose else 0),
                "gadi_apply")
     return y
+
+
+def residual(problem: Problem, b, x, u_r="f64", stream=None):
+    """r = b - A x on the device, in FP64 (u_r = "f64") or extra precision ("f64x2")."""
+    import torch
+    lib = _lib.load()
+    _check_dense(problem, b, x)
+    r = torch.empty_like(x)
+    _lib.check(lib.gadi_residual(C.byref(problem.c_struct()), C.c_void_p(_stream_handle(stream)),
+                                 C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(r.data_ptr()),
+                                 PREC[u_r] if isinstance(u_r, str) else int(u_r)),
+               "gadi_residual")
+    return r
 
 
 def autotune(problem: Problem, b, x, stream=None, **params):

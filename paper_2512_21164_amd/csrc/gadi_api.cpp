@@ -49,6 +49,7 @@ constexpr int64_t kHistCap = 1 << 20;
 
 struct Layout {
   int dim, cplx, us;
+  int xr;                // residual with Dot2 sums (u_r = GADI_F64X2)
   int nx, ny, nz;
   int64_t P, nvec, n;
   int ny_plane, nm, RY, L, Lo, nwy;
@@ -118,8 +119,9 @@ gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
   if (vs != GADI_OK) return vs;
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(GADI_ERR_INVALID_ARG, "alpha must be > 0");
   if (!(p->omega >= 0.0 && p->omega < 2.0)) return fail(GADI_ERR_INVALID_ARG, "omega must lie in [0, 2)");
-  if (p->u_r != GADI_F64 || p->u != GADI_F64)
-    return fail(GADI_ERR_UNSUPPORTED, "u_r and u must be GADI_F64");
+  if (p->u != GADI_F64) return fail(GADI_ERR_UNSUPPORTED, "u must be GADI_F64");
+  if (p->u_r != GADI_F64 && p->u_r != GADI_F64X2)
+    return fail(GADI_ERR_UNSUPPORTED, "u_r must be GADI_F64 or GADI_F64X2");
   if (p->u_s < GADI_F64 || p->u_s > GADI_BF16) return fail(GADI_ERR_INVALID_ARG, "unknown u_s");
   if (!(p->tol >= 0.0)) return fail(GADI_ERR_INVALID_ARG, "tol must be >= 0");
   if (p->max_outer < 0) return fail(GADI_ERR_INVALID_ARG, "max_outer must be >= 0");
@@ -184,10 +186,10 @@ gadi_status safeguarded_alpha(const gadi_stencil* st, const gadi_params& p, doub
 
 // Waves of one kernel class resident on the whole device (with a fallback
 // when no device is visible, e.g. for workspace sizing on a build host).
-int64_t resident_waves(int us, int cplx, int dim, int ry) {
+int64_t resident_waves(int us, int cplx, int dim, int ry, int xr) {
   static std::mutex mu;
   static std::map<int, int64_t> cache;
-  const int key = ((us * 2 + cplx) * 4 + dim) * 8 + ry;
+  const int key = (((us * 2 + cplx) * 4 + dim) * 8 + ry) * 2 + xr;
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
@@ -195,7 +197,7 @@ int64_t resident_waves(int us, int cplx, int dim, int ry) {
   int64_t waves = 256 * 4 * 4;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
-    const int nb = step_blocks_per_cu(us, cplx, dim, ry);
+    const int nb = step_blocks_per_cu(us, cplx, dim, ry, xr);
     if (nb > 0) waves = (int64_t)cus * nb * 4;
   } else {
     (void)hipGetLastError();
@@ -209,6 +211,7 @@ int default_ry(int, int) { return 1; }
 Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   Layout l{};
   l.dim = st->dim; l.cplx = st->is_complex ? 1 : 0; l.us = p->u_s;
+  l.xr = p->u_r == GADI_F64X2 ? 1 : 0;
   l.nx = (int)st->n[0]; l.ny = (int)st->n[1]; l.nz = (int)st->n[2];
   l.P = (l.nx + 7) / 8 * 8;
   l.n = (int64_t)l.nx * l.ny * l.nz;
@@ -226,7 +229,7 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   // Chunk length of a tiling: one full round of resident waves (CUs x
   // resident blocks x 4 wave tiles), so that no launch ends with a partial
   // round.  tile_chunk overrides it for the inner tiling.
-  const int64_t waves = resident_waves(l.us, l.cplx, l.dim, l.RY);
+  const int64_t waves = resident_waves(l.us, l.cplx, l.dim, l.RY, l.xr);
   auto one_round = [&](int V) -> int {
     const int64_t nwx = (l.nx + 64 * V - 1) / (64 * V);
     const int64_t per_plane = nwx * l.nwy;
@@ -315,7 +318,7 @@ void fill_desc(GadiDesc& d, const Layout& l, const gadi_stencil* st, const gadi_
   d.hist = reinterpret_cast<double*>(ws + l.o_hist);
 }
 
-int kernel_class_key(const Layout& l) { return ((l.us * 2 + l.cplx) * 4 + l.dim) * 8 + l.RY; }
+int kernel_class_key(const Layout& l) { return (((l.us * 2 + l.cplx) * 4 + l.dim) * 8 + l.RY) * 2 + l.xr; }
 
 }  // namespace
 
@@ -362,7 +365,7 @@ gadi_status launch_steps(gadi_handle* h, int count) {
   const int grid = (h->lay.max_tiles + 7) / 8 * 8;
   for (int i = 0; i < count; ++i) {
     const StepArgs args{h->d_table, h->d_desc, h->d_ctl};
-    hipError_t e = launch_step(h->lay.us, h->lay.cplx, h->lay.dim, h->lay.RY, args, grid, h->stream);
+    hipError_t e = launch_step(h->lay.us, h->lay.cplx, h->lay.dim, h->lay.RY, h->lay.xr, args, grid, h->stream);
     if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("step launch: ") + hipGetErrorString(e));
   }
   h->steps += count;
@@ -636,6 +639,7 @@ gadi_status gadi_set_params(gadi_handle* h, const gadi_params* p) {
   gadi_status s = validate(&h->st, p);
   if (s != GADI_OK) return s;
   if (p->u_s != h->p.u_s) return fail(GADI_ERR_INVALID_ARG, "u_s cannot change");
+  if (p->u_r != h->p.u_r) return fail(GADI_ERR_INVALID_ARG, "u_r cannot change");
   Layout l = make_layout(&h->st, p);
   if (l.total > h->ws_bytes || l.max_tiles != h->lay.max_tiles || l.RY != h->lay.RY || l.L != h->lay.L ||
       l.Lo != h->lay.Lo)
@@ -715,12 +719,26 @@ gadi_status gadi_destroy(gadi_handle* h) {
   return GADI_OK;
 }
 
-gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x, void* d_y, int32_t transpose) {
-  if (!st || !d_x || !d_y) return fail(GADI_ERR_INVALID_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+// Grid checks of the dense utility entry points (one thread per unknown).
+gadi_status check_dense_grid(const gadi_stencil* st) {
   if (st->dim != 2 && st->dim != 3) return fail(GADI_ERR_INVALID_ARG, "dim must be 2 or 3");
   for (int d = 0; d < 3; ++d)
-    if (st->n[d] < 1) return fail(GADI_ERR_INVALID_ARG, "grid sizes must be >= 1");
+    if (st->n[d] < 1 || st->n[d] > INT32_MAX) return fail(GADI_ERR_INVALID_ARG, "grid sizes must lie in [1, 2^31)");
   if (st->dim == 2 && st->n[2] != 1) return fail(GADI_ERR_INVALID_ARG, "2D problems need n[2] == 1");
+  if (st->n[0] * st->n[1] > INT64_MAX / st->n[2]) return fail(GADI_ERR_INVALID_ARG, "grid too large");
+  return GADI_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x, void* d_y, int32_t transpose) {
+  if (!st || !d_x || !d_y) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  gadi_status s = check_dense_grid(st);
+  if (s != GADI_OK) return s;
   if (d_x == d_y) return fail(GADI_ERR_INVALID_ARG, "x and y must not overlap");
   double lo[3] = {st->lo[0], st->lo[1], st->dim == 3 ? st->lo[2] : 0.0};
   double hi[3] = {st->hi[0], st->hi[1], st->dim == 3 ? st->hi[2] : 0.0};
@@ -728,6 +746,21 @@ gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x
                              lo, hi, st->is_complex ? st->shift_im : 0.0, transpose ? 1 : 0,
                              static_cast<const double*>(d_x), static_cast<double*>(d_y),
                              static_cast<hipStream_t>(hip_stream)));
+  return GADI_OK;
+}
+
+gadi_status gadi_residual(const gadi_stencil* st, void* hip_stream, const void* d_b, const void* d_x, void* d_r,
+                          int32_t u_r) {
+  if (!st || !d_b || !d_x || !d_r) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  gadi_status s = check_dense_grid(st);
+  if (s != GADI_OK) return s;
+  if (u_r != GADI_F64 && u_r != GADI_F64X2) return fail(GADI_ERR_INVALID_ARG, "u_r must be GADI_F64 or GADI_F64X2");
+  if (d_r == d_b || d_r == d_x) return fail(GADI_ERR_INVALID_ARG, "r must not overlap b or x");
+  HIP_TRY(launch_residual_dense(st->is_complex ? 1 : 0, u_r == GADI_F64X2 ? 1 : 0, st->dim, (int)st->n[0],
+                                (int)st->n[1], (int)st->n[2], st->center, st->lo, st->hi,
+                                st->is_complex ? st->shift_im : 0.0, static_cast<const double*>(d_b),
+                                static_cast<const double*>(d_x), static_cast<double*>(d_r),
+                                static_cast<hipStream_t>(hip_stream)));
   return GADI_OK;
 }
 
@@ -744,7 +777,7 @@ namespace {
 
 struct ClassGroup {
   int key;
-  int us, cplx, dim, ry;
+  int us, cplx, dim, ry, xr;
   int nsys;
   BatchTable* d_table;        // device table header
   GadiDesc** d_desc;          // device array of descriptor pointers
@@ -793,7 +826,7 @@ gadi_status rebuild_tables(gadi_batch* b) {
     ClassGroup g{};
     const Layout& l0 = b->member[kv.second[0]]->lay;
     g.key = kv.first;
-    g.us = l0.us; g.cplx = l0.cplx; g.dim = l0.dim; g.ry = l0.RY;
+    g.us = l0.us; g.cplx = l0.cplx; g.dim = l0.dim; g.ry = l0.RY; g.xr = l0.xr;
     g.nsys = (int)kv.second.size();
     char* base = b->ws + gi * group_bytes(b->max_sys);
     g.d_table = reinterpret_cast<BatchTable*>(base);
@@ -844,7 +877,7 @@ gadi_status rebuild_tables(gadi_batch* b) {
 gadi_status launch_groups(gadi_batch* b, int nsteps) {
   for (int s = 0; s < nsteps; ++s)
     for (auto& g : b->groups) {
-      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, StepArgs{g.d_table, g.one, g.one_ctl}, kGroupGrid, b->stream);
+      hipError_t e = launch_step(g.us, g.cplx, g.dim, g.ry, g.xr, StepArgs{g.d_table, g.one, g.one_ctl}, kGroupGrid, b->stream);
       if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("batch step: ") + hipGetErrorString(e));
     }
   return GADI_OK;

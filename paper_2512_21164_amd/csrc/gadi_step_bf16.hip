@@ -1,9 +1,6 @@
-// Step-kernel instantiations for u_s element type bf16.
+// Step-kernel instantiations for u_s element type BF16 storage (FP32 arithmetic), FP64 residual.
 #include "gadi_step.inc"
 
 namespace gadi {
-hipError_t launch_step_bf16(int dim, int ry, const StepArgs& args, int grid, hipStream_t st) {
-  return launch_step_dim<bf16>(dim, ry, args, grid, st);
-}
-int occupancy_bf16(int dim, int ry) { return occupancy_dim<bf16>(dim, ry); }
+GADI_STEP_INSTANCE(bf16, bf16, false)
 }  // namespace gadi

@@ -1,9 +1,6 @@
-// Step-kernel instantiations for u_s element type double.
+// Step-kernel instantiations for u_s element type float64, FP64 residual.
 #include "gadi_step.inc"
 
 namespace gadi {
-hipError_t launch_step_f64(int dim, int ry, const StepArgs& args, int grid, hipStream_t st) {
-  return launch_step_dim<double>(dim, ry, args, grid, st);
-}
-int occupancy_f64(int dim, int ry) { return occupancy_dim<double>(dim, ry); }
+GADI_STEP_INSTANCE(f64, double, false)
 }  // namespace gadi

@@ -55,7 +55,8 @@ def test_workspace_size_scales_with_precision():
 
 
 @pytest.mark.parametrize("bad", [dict(alpha=0.0), dict(alpha=-1.0), dict(omega=2.0), dict(omega=-0.1),
-                                 dict(u_r=1), dict(u=2), dict(u_s=7), dict(max_inner_h=0),
+                                 dict(u_r=1), dict(u_r=4), dict(u=2), dict(u=3), dict(u_s=3), dict(u_s=7),
+                                 dict(max_inner_h=0),
                                  dict(tile_ry=3), dict(tol=-1.0), dict(normA=-1.0), dict(max_restarts=-1),
                                  dict(alpha_growth=1.0), dict(u_s="bf16", safeguard_tau=1e-3),
                                  dict(safeguard_tau=-1.0)])
@@ -63,6 +64,27 @@ def test_argument_errors(bad):
     pr = api.Problem.convection_diffusion(2, 32, 1.0)
     with pytest.raises(_lib.GadiError):
         _ws(pr, **bad)
+
+
+def test_extra_precision_residual_is_accepted_and_sized_like_fp64():
+    pr = api.Problem.convection_diffusion(2, 96, 3.0)
+    for us in ("f64", "f32", "bf16"):
+        assert _ws(pr, u_s=us, u_r="f64x2") == _ws(pr, u_s=us, u_r="f64")
+
+
+def test_residual_argument_errors():
+    """gadi_residual validates before any device work (the pointers are never used)."""
+    lib = _lib.load()
+    st = api.Problem.convection_diffusion(2, 16, 1.0).c_struct()
+    p1, p2, p3 = C.c_void_p(16), C.c_void_p(32), C.c_void_p(48)
+    assert lib.gadi_residual(C.byref(st), None, p1, p2, p3, 7) == _lib.GADI_ERR_INVALID_ARG
+    assert lib.gadi_residual(C.byref(st), None, p1, p2, p3, _lib.GADI_F32) == _lib.GADI_ERR_INVALID_ARG
+    assert lib.gadi_residual(C.byref(st), None, p1, p2, p1, _lib.GADI_F64X2) == _lib.GADI_ERR_INVALID_ARG
+    assert lib.gadi_residual(C.byref(st), None, p1, p2, p2, _lib.GADI_F64) == _lib.GADI_ERR_INVALID_ARG
+    assert lib.gadi_residual(C.byref(st), None, None, p2, p3, _lib.GADI_F64X2) == _lib.GADI_ERR_INVALID_ARG
+    assert lib.gadi_residual(None, None, p1, p2, p3, _lib.GADI_F64X2) == _lib.GADI_ERR_INVALID_ARG
+    flat = api.Problem(2, (8, 8, 2), 4.0, (-1, -1, 0), (-1, -1, 0)).c_struct()
+    assert lib.gadi_residual(C.byref(flat), None, p1, p2, p3, _lib.GADI_F64X2) == _lib.GADI_ERR_INVALID_ARG
 
 
 def test_problem_errors():

@@ -31,6 +31,30 @@ def x_true(n: int, seed: int = 0, dist: str = "uniform") -> np.ndarray:
     raise ValueError(f"unknown distribution {dist!r}")
 
 
+def dyadic_field(n, bits: int = 24, seed: int = 0) -> np.ndarray:
+    """Smooth seeded grid function with few significant bits, x-fastest.
+
+    n = (nx, ny, nz): a seeded amplitude in [0.5, 1] times the product over
+    the axes of length > 1 of sin(pi t_d) (t_d the interior grid coordinates):
+    the smoothest mode, for which ||b|| = ||A x|| is smallest against
+    ||A|| ||x||, rounded to a multiple of 2^-bits.  With dyadic stencil coefficients, A applied to it is exactly
+    representable in float64, so b = A x is exact and x is the exact solution
+    of the float64 system.
+    """
+    rng = np.random.default_rng(seed)
+    f = np.full(1, rng.uniform(0.5, 1.0))
+    for m in n:
+        t = np.arange(1, m + 1) / (m + 1)
+        f = np.multiply.outer(np.sin(np.pi * t) if m > 1 else np.ones(1), f)
+    return np.round(f.ravel() * 2.0 ** bits) / 2.0 ** bits
+
+
+def perturbation(n: int, scale: float, seed: int = 0) -> np.ndarray:
+    """Seeded float64 vector with entries scale * U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    return scale * rng.uniform(-1.0, 1.0, size=n)
+
+
 def complex_rhs(n: int, seed: int = 0) -> np.ndarray:
     """Seeded complex right-hand side, real and imaginary parts ~ U(-1, 1)."""
     rng = np.random.default_rng(seed)
