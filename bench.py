@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--us", default="f32", choices=["bf16", "f32"], help="inner precision of the mixed solve")
+    ap.add_argument("--u-r", default="f64", choices=["f64", "f64x2"],
+                    help="residual precision u_r: FP64, or FP64 pairs (extra precision) for both solves")
     ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--alpha", type=float, default=None)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -95,11 +97,13 @@ def alg_bytes(hist, n, s, w=8, cplx=False):
 
 
 def kernel_sources_sha256():
-    """Hash of the HIP sources and the C-ABI header (the traffic record is valid only for these)."""
+    """Hash of the sources of the step kernel and of its launch configuration (tilings,
+    grid, chunking): the traffic record is valid only for these."""
     import glob
     import hashlib
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2512_21164_amd", "csrc", "*")))
-    files.append(os.path.join(ROOT, "include", "gadi.h"))
+    csrc = os.path.join(ROOT, "paper_2512_21164_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "gadi_step*")))
+    files += [os.path.join(csrc, f) for f in ("gadi_kernels.hip", "gadi_internal.h", "gadi_launch.h", "gadi_api.cpp")]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -108,7 +112,7 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload, us, alpha, beta, inner_tol):
+def measured_traffic(workload, us, alpha, beta, inner_tol, u_r="f64"):
     """HBM bytes per step launch from the committed rocprofv3 counter runs, or None.
 
     The record (profiles/gadi_step_<us>_2d4096_traffic.json) holds FETCH_SIZE + WRITE_SIZE per
@@ -122,6 +126,7 @@ def measured_traffic(workload, us, alpha, beta, inner_tol):
         rec = json.load(fh)
     same = (rec.get("workload") == workload and rec.get("u_s") == us and abs(rec.get("alpha", -1) - alpha) < 1e-12
             and abs(rec.get("beta", -1) - beta) < 1e-12 and abs(rec.get("inner_tol", -1) - inner_tol) < 1e-15
+            and rec.get("u_r", "f64") == u_r
             and rec.get("source_sha256") == kernel_sources_sha256())
     return float(rec["traffic_bytes_per_launch"]) if same else None
 
@@ -174,7 +179,7 @@ def main():
     nxt = torch.linalg.norm(xt)
 
     def run(us, steps, warmup):
-        s = Solver(pr, alpha=alpha, omega=1.0, u_s=us, tol=args.tol, max_outer=args.max_outer,
+        s = Solver(pr, alpha=alpha, omega=1.0, u_s=us, u_r=args.u_r, tol=args.tol, max_outer=args.max_outer,
                    inner_tol_h=args.inner_tol, inner_tol_s=args.inner_tol)
         reps = []
         x = torch.zeros_like(b)
@@ -215,9 +220,10 @@ def main():
         "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": f"f64+{args.us}", "data": "synthetic",
         "config": {"workload": f"{desc}, beta=({beta},{beta}{',' + str(beta) if dim == 3 else ''}), "
-                               f"alpha={alpha}, omega=1, inner tolerance {args.inner_tol}, target backward error {args.tol}",
+                               f"alpha={alpha}, omega=1, inner tolerance {args.inner_tol}, target backward error {args.tol}"
+                               + (", residual in FP64 pairs" if args.u_r == "f64x2" else ""),
                    "grid": [ng] * dim, "unknowns": n, "inner_precision": args.us, "alpha": alpha, "beta": beta,
-                   "inner_tol": args.inner_tol},
+                   "inner_tol": args.inner_tol, "residual_precision": args.u_r},
         "time_to_solution_s": el / args.steps,
         "mixed": {"u_s": args.us, "status": rep["status_name"], "outer": rep["outer"], "inner_h": rep["inner_h"],
                   "inner_s": rep["inner_s"], "be": rep["be"], "forward_error": fe, "solve_ms": rep["ms"],
@@ -231,11 +237,11 @@ def main():
                        "inner_s": r64["inner_s"], "be": r64["be"], "forward_error": fe64,
                        "alg_bytes_per_solve": alg_bytes(h64, n, 8)}
         out["speedup_mixed_vs_fp64"] = value / out["fp64"]["solves_per_s"]
-    kname = {"bf16": "gadi::gadi_step<gadi::bf16, %d, %d>", "f32": "gadi::gadi_step<float, %d, %d>"}[args.us]
+    kname = {"bf16": "gadi::gadi_step<gadi::bf16, %d, %d, %s>", "f32": "gadi::gadi_step<float, %d, %d, %s>"}[args.us]
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": measured_traffic(args.workload, args.us, alpha, beta, args.inner_tol),
-                       "kernel": kname % (dim, 1 if dim == 2 else 0),
+                       "traffic": measured_traffic(args.workload, args.us, alpha, beta, args.inner_tol, args.u_r),
+                       "kernel": kname % (dim, 1, "true" if args.u_r == "f64x2" else "false"),
                        "avg_launch_us": avg_launch_us, "alg_bytes_per_launch": bytes_solve / launches}
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -248,6 +254,8 @@ def main():
         ms = int(round(rep["inner_s"] / max(1, rep["outer"])))
         out["cpu_baseline"] = cpu_baseline(dim, ng, beta, alpha, x_np, mh, ms, args.cpu_sweeps, args.us,
                                            int(rep["outer"]), normA)
+        if args.u_r != "f64":
+            out["cpu_baseline"]["sample"] += "; the oracle forms the residual in FP64 (its exact residual is not timed)"
         print("[bench] CPU oracle baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
