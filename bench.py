@@ -51,7 +51,10 @@ def parse():
     ap.add_argument("--u-r", default="f64", choices=["f64", "f64x2"],
                     help="residual precision u_r: FP64, or FP64 pairs (extra precision) for both solves")
     ap.add_argument("--beta", type=float, default=None)
-    ap.add_argument("--alpha", type=float, default=None)
+    ap.add_argument("--alpha", default=None,
+                    help="regularization alpha (a number), or 'gpr' for the packaged Section 4.2 model")
+    ap.add_argument("--max-restarts", type=int, default=0,
+                    help="alpha restarts on stagnation or divergence (Section 4.3, step 3)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--inner-tol", type=float, default=1e-2,
                     help="relative-residual tolerance of both inner solves (the paper picks it from 1e-2..1e-6)")
@@ -168,8 +171,16 @@ def main():
 
     dim, ng, beta0, alpha0, desc = WORKLOADS[args.workload]
     beta = beta0 if args.beta is None else args.beta
-    alpha = alpha0 if args.alpha is None else args.alpha
     pr = Problem.convection_diffusion(dim, ng, beta)
+    alpha_source = "fixed"
+    if args.alpha is None:
+        alpha = alpha0
+    elif args.alpha == "gpr":
+        from paper_2512_21164_amd.alpha_gpr import predict_alpha
+        alpha = predict_alpha(pr, args.us)
+        alpha_source = "gpr"
+    else:
+        alpha = float(args.alpha)
     n = pr.size
     dev = torch.device("cuda:0")
     x_np = workloads.x_true(n, 0, "normal" if dim == 3 else "uniform")
@@ -180,7 +191,7 @@ def main():
 
     def run(us, steps, warmup):
         s = Solver(pr, alpha=alpha, omega=1.0, u_s=us, u_r=args.u_r, tol=args.tol, max_outer=args.max_outer,
-                   inner_tol_h=args.inner_tol, inner_tol_s=args.inner_tol)
+                   inner_tol_h=args.inner_tol, inner_tol_s=args.inner_tol, max_restarts=args.max_restarts)
         reps = []
         x = torch.zeros_like(b)
         for _ in range(warmup):
@@ -223,11 +234,13 @@ def main():
                                f"alpha={alpha}, omega=1, inner tolerance {args.inner_tol}, target backward error {args.tol}"
                                + (", residual in FP64 pairs" if args.u_r == "f64x2" else ""),
                    "grid": [ng] * dim, "unknowns": n, "inner_precision": args.us, "alpha": alpha, "beta": beta,
-                   "inner_tol": args.inner_tol, "residual_precision": args.u_r},
+                   "inner_tol": args.inner_tol, "residual_precision": args.u_r, "alpha_source": alpha_source,
+                   "max_restarts": args.max_restarts},
         "time_to_solution_s": el / args.steps,
         "mixed": {"u_s": args.us, "status": rep["status_name"], "outer": rep["outer"], "inner_h": rep["inner_h"],
                   "inner_s": rep["inner_s"], "be": rep["be"], "forward_error": fe, "solve_ms": rep["ms"],
-                  "kernel_ms": rep["kernel_ms"], "launches": rep["steps"], "alg_bytes_per_solve": bytes_solve},
+                  "kernel_ms": rep["kernel_ms"], "launches": rep["steps"], "alg_bytes_per_solve": bytes_solve,
+                  "alpha_final": rep["alpha"], "restarts": rep["restarts"]},
     }
     if args.fp64_steps > 0:
         el64, reps64, fe64, _ = run("f64", args.fp64_steps, 0)
@@ -238,8 +251,11 @@ def main():
                        "alg_bytes_per_solve": alg_bytes(h64, n, 8)}
         out["speedup_mixed_vs_fp64"] = value / out["fp64"]["solves_per_s"]
     kname = {"bf16": "gadi::gadi_step<gadi::bf16, %d, %d, %s>", "f32": "gadi::gadi_step<float, %d, %d, %s>"}[args.us]
+    if any(r["restarts"] > 0 for r, _ in reps):
+        # the sweep history holds the last attempt only: the bytes of a restarted solve are not known
+        achieved = None
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS,
+                       "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                        "traffic": measured_traffic(args.workload, args.us, alpha, beta, args.inner_tol, args.u_r),
                        "kernel": kname % (dim, 1, "true" if args.u_r == "f64x2" else "false"),
                        "avg_launch_us": avg_launch_us, "alg_bytes_per_launch": bytes_solve / launches}

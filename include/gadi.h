@@ -237,6 +237,36 @@ gadi_status gadi_apply(const gadi_stencil* st, void* hip_stream, const void* d_x
 gadi_status gadi_residual(const gadi_stencil* st, void* hip_stream, const void* d_b, const void* d_x, void* d_r,
                           int32_t u_r);
 
+/* ---- data-driven initial alpha (Section 4.2) -------------------------------
+ * Section 4.3 starts the alpha selection from a regression model trained on
+ * small problems.  Features of a problem (closed forms of the stencil, host
+ * only, no device work):
+ *   f[0] = log10 lambda_min(M), f[1] = log10 lambda_max(M)      M = (A + A^H)/2
+ *   f[2] = log10 max(rho(N), 1e-12)                               N = (A - A^H)/2
+ *   f[3] = log10 of the unit roundoff of u_s (Table 1)
+ * (per-axis Toeplitz eigenvalues summed over the axes; rho(N) adds |shift_im|
+ * for complex problems).  GADI_ERR_UNSUPPORTED if M is not positive
+ * definite, GADI_ERR_INVALID_ARG for an invalid grid or u_s. */
+gadi_status gadi_alpha_features(const gadi_stencil* st, int32_t u_s, double f[4]);
+
+/* Gaussian-process regression of log10(alpha_opt) on the features: linear
+ * mean [1, f0, f1, f2, f3]^T b with b estimated from the data (flat prior),
+ * squared-exponential covariance sf^2 exp(-1/2 sum_i ((f_i - f'_i)/l_i)^2)
+ * and noise variance sn^2 (Rasmussen and Williams 2006, Section 2.7).
+ * X: n_train x 4 features (row-major, host), y: n_train targets log10(alpha),
+ * hyper = {l_0, l_1, l_2, l_3, sf, sn}, all > 0; n_train in [6, 4096].  The
+ * model copies its inputs and factors them once (O(n_train^3) host work).
+ * GADI_ERR_INVALID_ARG for bad sizes, non-finite or non-positive inputs, or a
+ * covariance / basis matrix that is not positive definite. */
+typedef struct gadi_alpha_gpr gadi_alpha_gpr;
+gadi_status gadi_alpha_gpr_create(int32_t n_train, const double* X, const double* y, const double hyper[6],
+                                  gadi_alpha_gpr** out);
+/* Posterior mean of log10(alpha_opt) at features f, and (sd nullable) the
+ * posterior standard deviation of the latent function, basis uncertainty
+ * included. */
+gadi_status gadi_alpha_gpr_predict(const gadi_alpha_gpr* m, const double f[4], double* log10_alpha, double* sd);
+gadi_status gadi_alpha_gpr_destroy(gadi_alpha_gpr* m);
+
 /* ---- batched execution ------------------------------------------------------
  * A batch advances many handles together: one device step launch per
  * (precision, dimension, tile shape) class moves every member by one phase

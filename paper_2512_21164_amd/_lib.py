@@ -75,6 +75,10 @@ SIGNATURES = [
     ("gadi_destroy", C.c_int32, [_P]),
     ("gadi_apply", C.c_int32, [_S, _P, _P, _P, C.c_int32]),
     ("gadi_residual", C.c_int32, [_S, _P, _P, _P, _P, C.c_int32]),
+    ("gadi_alpha_features", C.c_int32, [_S, C.c_int32, _D]),
+    ("gadi_alpha_gpr_create", C.c_int32, [C.c_int32, _D, _D, _D, C.POINTER(_P)]),
+    ("gadi_alpha_gpr_predict", C.c_int32, [_P, _D, _D, _D]),
+    ("gadi_alpha_gpr_destroy", C.c_int32, [_P]),
     ("gadi_batch_workspace_bytes", C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
     ("gadi_batch_create", C.c_int32, [C.c_int32, _P, _P, C.c_size_t, C.POINTER(_P)]),
     ("gadi_batch_add", C.c_int32, [_P, _P, _P, _P, _I]),

@@ -521,6 +521,12 @@ const char* gadi_status_string(gadi_status s) {
   }
 }
 
+}  // extern "C"
+
+int32_t gadi::set_error(int32_t status, const char* msg) { return fail(status, msg ? msg : ""); }
+
+extern "C" {
+
 const char* gadi_last_error(void) { return g_last_error.c_str(); }
 
 void gadi_params_default(gadi_params* p) {

@@ -137,4 +137,8 @@ struct StepArgs {
   const GadiCtl* one_ctl;
 };
 
+// Host: record the message returned by gadi_last_error() and pass the status on
+// (for the C-ABI entry points outside gadi_api.cpp).
+int32_t set_error(int32_t status, const char* msg);
+
 }  // namespace gadi
