@@ -181,3 +181,33 @@ def test_packaged_model_is_consistent():
     mu_ref, _ = gpr.posterior(X, y, hyper, X[:5])
     for i in range(5):
         assert model.predict_features(X[i])[0] == pytest.approx(mu_ref[i], rel=1e-9, abs=1e-10)
+
+
+@pytest.mark.gpu
+def test_gpu_predicted_alpha_is_near_the_best_grid_alpha(gpu_lib):
+    """On a problem outside the training set (2D 640^2, beta = 10, FP32 inner solves), the
+    packaged model's alpha converges to BE 1e-10 and its algorithmic cost is within 2x of the
+    best alpha of the grid within a decade of it."""
+    import torch
+
+    import workloads
+    from paper_2512_21164_amd import Solver, apply
+    pr = Problem.convection_diffusion(2, 640, 10.0)
+    a_pred = alpha_gpr.predict_alpha(pr, "f32")
+    xt = torch.from_numpy(workloads.x_true(pr.size, 0)).to("cuda")
+    b = apply(pr, xt)
+    kw = dict(u_s="f32", tol=1e-10, max_outer=6000, inner_tol_h=1e-2, inner_tol_s=1e-2)
+    s = Solver(pr, alpha=a_pred, **kw)
+    cost = {}
+    try:
+        grid = [a for a in alpha_gpr.ALPHAS if abs(math.log10(a / a_pred)) <= 1.0]
+        for a in [a_pred] + grid:
+            s.set_params(alpha=a, **kw)
+            _, rep = s.solve(b, torch.zeros_like(b))
+            ok = rep["status"] == _lib.GADI_OK
+            cost[a] = alpha_gpr.solve_cost(rep, "f32", False) if ok else math.inf
+            print(f"alpha {a:.4g}: {rep['status_name']} outer {rep['outer']} cost {cost[a]:.4g}", flush=True)
+    finally:
+        s.close()
+    assert math.isfinite(cost[a_pred])
+    assert cost[a_pred] <= 2.0 * min(cost[a] for a in grid)
