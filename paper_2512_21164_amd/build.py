@@ -17,8 +17,12 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgadi.so")
 ARCH = "gfx950"
 
+# The step kernel's three pointer arguments are preloaded into SGPRs at wave
+# launch (gfx950 kernarg preloading), which saves a dependent memory round trip
+# at the start of every launch.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-kernarg-preload-count=3",
          "-Wno-unused-command-line-argument"]
 
 

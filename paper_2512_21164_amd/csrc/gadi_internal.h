@@ -24,7 +24,9 @@
 #define GADI_BF16_V 4
 #endif
 
-#define GADI_TICKET_GROUPS 64
+#ifndef GADI_TICKET_GROUPS
+#define GADI_TICKET_GROUPS 16
+#endif
 // bytes of the ticket counters of one system: a top counter and
 // GADI_TICKET_GROUPS group counters, 256 bytes apart
 #define GADI_TICKET_BYTES (256 * (1 + GADI_TICKET_GROUPS))
