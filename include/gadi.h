@@ -7,7 +7,7 @@
  *               with the Hermitian / skew-Hermitian choice
  *               M = (A + A^H)/2, N = (A - A^H)/2                  Sections 5.2-5.4
  *   iteration   Algorithm 1 (Section 2.3): from x^(0),
- *                 r = b - A x           in u_r  (FP64 here)
+ *                 r = b - A x           in u_r  (FP64, or FP64 pairs: GADI_F64X2)
  *                 solve H z = r         in u_s  (CG, Section 5.1)
  *                 solve S y = (2-omega) alpha z   in u_s  (CG on the normal equations)
  *                 x = x + y             in u    (FP64 here)

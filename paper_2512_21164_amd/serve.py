@@ -8,6 +8,12 @@ batch), and adds it to the batch, whose members keep their Krylov state
 resident until they finish.  Between step launches finished members are
 retired and their memory is released.  The loop reports per-request latency
 (arrival to result), p50 / p99, and solves per second over the makespan.
+
+Each request carries its own alpha; with ``alpha_source="gpr"`` the server
+instead starts every request from the alpha that the packaged regression
+model predicts for it (Section 4.2; the model was trained with FP32 and BF16
+inner solves, so FP64 inner solves take the FP32 prediction, where the
+kappa(H) kappa(S) u_s term is already negligible).
 """
 from __future__ import annotations
 
@@ -51,7 +57,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, u_s: str = "f64", tol: float = 1e-10,
                  max_outer: int = 20000, norm_iters: int = 30, steps_per_launch: int = 16, device="cuda",
-                 keep_solutions: bool = False):
+                 keep_solutions: bool = False, alpha_source: str = "request"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -65,10 +71,26 @@ class Server:
         self.keep = keep_solutions
         self.solutions: Dict[int, np.ndarray] = {}
         self.max_used = 0
+        if alpha_source not in ("request", "gpr"):
+            raise ValueError("alpha_source must be 'request' or 'gpr'")
+        self.model = None
+        if alpha_source == "gpr":
+            from .alpha_gpr import Model
+            self.model = Model.load()
+        self._alpha_cache: Dict[int, float] = {}
+
+    def alpha(self, req) -> float:
+        """The request's alpha, or the model's prediction for its problem."""
+        if self.model is None:
+            return req.alpha
+        if req.rid not in self._alpha_cache:
+            us = self.params["u_s"]
+            self._alpha_cache[req.rid] = self.model.predict(request_problem(req), "f32" if us == "f64" else us)[0]
+        return self._alpha_cache[req.rid]
 
     def footprint(self, req) -> int:
         pr = request_problem(req)
-        p = make_params(alpha=req.alpha, **self.params)
+        p = make_params(alpha=self.alpha(req), **self.params)
         return workspace_bytes(pr, p) + 3 * 8 * pr.size     # workspace + b, x, x_true
 
     def _start(self, req):
@@ -79,7 +101,7 @@ class Server:
             xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).to(self.device, non_blocking=False)
             b = apply(pr, xt, stream=self.side)
             x = torch.zeros_like(b)
-            s = Solver(pr, stream=self.side, device=self.device, alpha=req.alpha, **self.params)
+            s = Solver(pr, stream=self.side, device=self.device, alpha=self.alpha(req), **self.params)
         self.side.synchronize()
         return s, b, x, xt
 
@@ -135,6 +157,8 @@ class Server:
 
     def close(self):
         self.batch.close()
+        if self.model is not None:
+            self.model.close()
 
 
 def summarize(results: List[Result]) -> dict:
@@ -178,13 +202,15 @@ def main(argv=None):
     ap.add_argument("--max-outer", type=int, default=20000)
     ap.add_argument("--steps-per-launch", type=int, default=16)
     ap.add_argument("--us", default="bf16,f64", help="comma-separated inner precisions to run, in order")
+    ap.add_argument("--alpha", default="request", choices=["request", "gpr"],
+                    help="alpha of each solve: the request's, or the packaged model's prediction")
     args = ap.parse_args(argv)
     trace = workloads.scale_trace(workloads.poisson_trace(args.requests, args.rate, args.seed),
                                   args.max_side2d, args.max_side3d)
     out = {}
     for us in args.us.split(","):
         srv = Server(int(args.budget_gb * 2 ** 30), max_slots=args.slots, u_s=us, max_outer=args.max_outer,
-                     steps_per_launch=args.steps_per_launch)
+                     steps_per_launch=args.steps_per_launch, alpha_source=args.alpha)
         done = [0]
 
         def log(r, us=us):
@@ -199,7 +225,8 @@ def main(argv=None):
         out[us] = summ
         srv.close()
     print(json.dumps({"serving": out, "requests": args.requests, "rate_per_s": args.rate,
-                      "max_side2d": args.max_side2d, "max_side3d": args.max_side3d, "max_outer": args.max_outer}))
+                      "max_side2d": args.max_side2d, "max_side3d": args.max_side3d, "max_outer": args.max_outer,
+                      "alpha": args.alpha}))
 
 
 if __name__ == "__main__":

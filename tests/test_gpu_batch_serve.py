@@ -112,3 +112,33 @@ def test_serving_loop_budget_and_solo_equality(gpu_lib):
         assert rep["status_name"] == r.status
         assert np.array_equal(x.cpu().numpy(), srv.solutions[r.rid])
     srv.close()
+
+
+def test_serving_with_predicted_alpha(gpu_lib):
+    """alpha_source="gpr": each request starts from the packaged model's alpha (Section 4.2);
+    the served result equals a solo solve with that alpha, bit for bit."""
+    import torch
+    from paper_2512_21164_amd import Solver, apply
+    from paper_2512_21164_amd.alpha_gpr import Model
+    from paper_2512_21164_amd.serve import Server, request_problem, summarize
+    trace = workloads.scale_trace(workloads.poisson_trace(num=8, rate_per_s=400.0, seed=5), 96, 24)
+    srv = Server(budget_bytes=1 << 30, max_slots=4, u_s="f32", max_outer=3000, keep_solutions=True,
+                 alpha_source="gpr")
+    res = srv.run(trace)
+    summ = summarize(res)
+    assert summ["completed"] == len(trace)
+    model = Model.load()
+    for r in res[:4]:
+        req = next(q for q in trace if q.rid == r.rid)
+        pr = request_problem(req)
+        a = model.predict(pr, "f32")[0]
+        assert srv.alpha(req) == a
+        xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).cuda()
+        b = apply(pr, xt)
+        s = Solver(pr, alpha=a, u_s="f32", tol=1e-10, max_outer=3000, norm_iters=30)
+        x, rep = s.solve(b, torch.zeros_like(b))
+        s.close()
+        assert rep["status_name"] == r.status
+        assert np.array_equal(x.cpu().numpy(), srv.solutions[r.rid])
+    model.close()
+    srv.close()
