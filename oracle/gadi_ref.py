@@ -24,7 +24,7 @@ and arithmetic, "bf16" BF16 storage (round-to-nearest-even after every
 vector update) with float32 arithmetic; the operator coefficients are held in
 the arithmetic format (float32 for f32 and bf16).
 
-Stopping and status rules of the outer loop (readings):
+Stopping and status rules of the outer loop (readings of Sections 3, 4.3 and 5.1):
 at the top of sweep k the residual of x^(k) is formed and
     BE_k = ||r|| / (||A|| ||x^(k)|| + ||b||)           (backward error, Section 3)
     relres_k = ||r|| / ||r^(0)||                        (the paper's Section 5 test)

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 Section 4.2 initialises alpha with a Gaussian-process regression (GPR) model
 trained on small problems.  The paper takes its model from a cited work that
-is not restated; the reading used here (listed in the design doc):
+is not restated; the reading used here:
 
 * features of a problem: log10 lambda_min(M), log10 lambda_max(M),
   log10 max(rho(N), 1e-12) and log10 u_s, with M, N the Hermitian and

@@ -6,7 +6,7 @@ convection-diffusion in Section 5.3, complex reaction-diffusion in Section
 5.4), scaled by h^2 as the paper does, on the interior of a uniform grid with
 homogeneous Dirichlet boundary values (h = 1/(n_g + 1)).
 
-Readings taken (listed in the design doc):
+Readings taken where the paper leaves the discretization open:
 * The convection term is discretized with the sign the PDE gives:
   for  -u'' + beta u'  the row of T_d is  lo = -1 - beta h/2 (coefficient of
   the i-1 neighbour), diag = 2, hi = -1 + beta h/2 (coefficient of i+1).
