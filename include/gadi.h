@@ -116,8 +116,8 @@ typedef struct {
   int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
                               4.3, step 3); 0 (default): none                            */
   double safeguard_tau;    /* > 0: before the solve, raise alpha until
-                              kappa(H) kappa(S) u_s < safeguard_tau (Section 4.3, step 2,
-                              eq. (239479)); 0 (default): no check.  Must exceed the unit
+                              kappa(H) kappa(S) u_s < safeguard_tau (the safety condition
+                              of Section 4.3, step 2); 0 (default): no check.  Must exceed the unit
                               roundoff of u_s (Table 1).                                  */
   double alpha_growth;     /* factor of each alpha increase, > 1; default 10^(3/7), one
                               step of eight log-spaced values per decade triple          */
