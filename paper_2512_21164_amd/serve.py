@@ -57,7 +57,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, u_s: str = "f64", tol: float = 1e-10,
                  max_outer: int = 20000, norm_iters: int = 30, steps_per_launch: int = 16, device="cuda",
-                 keep_solutions: bool = False, alpha_source: str = "request"):
+                 keep_solutions: bool = False, alpha_source: str = "request", stall_timeout_s=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -78,6 +78,9 @@ class Server:
             from .alpha_gpr import Model
             self.model = Model.load()
         self._alpha_cache: Dict[int, float] = {}
+        # failure detection: with requests on the device, at least one must finish
+        # within this many seconds, else run() raises (None: no limit)
+        self.stall_timeout_s = stall_timeout_s
 
     def alpha(self, req) -> float:
         """The request's alpha, or the model's prediction for its problem."""
@@ -115,6 +118,7 @@ class Server:
         results: List[Result] = []
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
+        last_progress = 0.0
         while pending or waiting or active:
             t = now()
             while pending and pending[0].arrival_s * time_scale <= t:
@@ -132,6 +136,7 @@ class Server:
                 waiting.popleft()
                 s, b, x, xt = self._start(req)
                 slot = self.batch.add(s, b, x)
+                last_progress = now()
                 used += fp
                 self.max_used = max(self.max_used, used)
                 active[slot] = (req, now(), fp, xt)
@@ -149,8 +154,13 @@ class Server:
                     s.close()
                     del s, b, x, xt
                     used -= fp
+                    last_progress = now()
                     if log:
                         log(results[-1])
+                if active and self.stall_timeout_s is not None and now() - last_progress > self.stall_timeout_s:
+                    stuck = sorted(req.rid for req, _, _, _ in active.values())
+                    raise RuntimeError(f"serving stalled: no request finished or was admitted for "
+                                       f"{now() - last_progress:.1f} s; active requests {stuck}")
             elif pending:
                 time.sleep(max(0.0, min(0.002, pending[0].arrival_s * time_scale - now())))
         return results
@@ -204,13 +214,16 @@ def main(argv=None):
     ap.add_argument("--us", default="bf16,f64", help="comma-separated inner precisions to run, in order")
     ap.add_argument("--alpha", default="request", choices=["request", "gpr"],
                     help="alpha of each solve: the request's, or the packaged model's prediction")
+    ap.add_argument("--stall-timeout", type=float, default=600.0,
+                    help="raise if no request finishes or is admitted for this many seconds (0: off)")
     args = ap.parse_args(argv)
     trace = workloads.scale_trace(workloads.poisson_trace(args.requests, args.rate, args.seed),
                                   args.max_side2d, args.max_side3d)
     out = {}
     for us in args.us.split(","):
         srv = Server(int(args.budget_gb * 2 ** 30), max_slots=args.slots, u_s=us, max_outer=args.max_outer,
-                     steps_per_launch=args.steps_per_launch, alpha_source=args.alpha)
+                     steps_per_launch=args.steps_per_launch, alpha_source=args.alpha,
+                     stall_timeout_s=args.stall_timeout if args.stall_timeout > 0 else None)
         done = [0]
 
         def log(r, us=us):

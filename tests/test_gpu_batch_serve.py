@@ -142,3 +142,24 @@ def test_serving_with_predicted_alpha(gpu_lib):
         assert np.array_equal(x.cpu().numpy(), srv.solutions[r.rid])
     model.close()
     srv.close()
+
+
+def test_serving_stall_watchdog_raises(gpu_lib):
+    """Failure detection, forced from the host: with a zero stall limit the loop raises as soon
+    as a step passes without a request finishing; the device stays usable."""
+    import torch
+    from paper_2512_21164_amd import Solver, apply
+    from paper_2512_21164_amd.serve import Server, request_problem
+    trace = workloads.scale_trace(workloads.poisson_trace(num=4, rate_per_s=1000.0, seed=7), 64, 16)
+    srv = Server(budget_bytes=1 << 30, max_slots=4, u_s="f32", max_outer=3000, stall_timeout_s=0.0)
+    with pytest.raises(RuntimeError, match="stalled"):
+        srv.run(trace)
+    torch.cuda.synchronize()
+    srv.close()
+    pr = request_problem(trace[0])
+    xt = torch.from_numpy(workloads.x_true(pr.size, 0)).cuda()
+    b = apply(pr, xt)
+    s = Solver(pr, alpha=trace[0].alpha, u_s="f32", tol=1e-8, max_outer=3000)
+    _, rep = s.solve(b, torch.zeros_like(b))
+    s.close()
+    assert rep["status"] in (0, 1, 2, 3)
