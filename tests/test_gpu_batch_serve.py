@@ -66,6 +66,34 @@ def test_batch_members_equal_solo_runs(gpu_lib):
     batch.close()
 
 
+def test_batch_many_members_of_one_class(gpu_lib):
+    """24 members of one kernel class (2D, FP32 inner solves, sides 130 to 199).  Each
+    member's wide tiling has twice the tiles of its inner one, so slots without a tile
+    in an inner phase hold a tile of the next outer phase, and 24 descriptors and
+    control blocks do not stay in the scalar cache: a slot that read a phase set
+    earlier in the same launch would run a tile of the next phase and offset the
+    member's ticket counters.  Every member must finish with its solo result."""
+    from paper_2512_21164_amd.batch import Batch
+    cases = [(2, 130 + 3 * i, 5.0, 0.02, "f32") for i in range(24)]
+    batch = Batch(32)
+    keep = {}
+    for i, c in enumerate(cases):
+        s, bd, xd, _ = _case(*c, seed=100 + i)
+        keep[batch.add(s, bd, xd)] = (i, s, xd)
+    reps = batch.run(steps_per_launch=16)
+    assert len(reps) == len(cases)
+    for slot, rep in reps.items():
+        i, s, xd = keep[slot]
+        s2, bd2, xd2, _ = _case(*cases[i], seed=100 + i)
+        x2, r2 = s2.solve(bd2, xd2)
+        assert rep["status"] == 0 and r2["status"] == 0, cases[i]
+        assert (rep["outer"], rep["inner_h"], rep["inner_s"]) == (r2["outer"], r2["inner_h"], r2["inner_s"])
+        assert np.array_equal(xd.cpu().numpy(), x2.cpu().numpy()), cases[i]
+        s.close()
+        s2.close()
+    batch.close()
+
+
 def test_batch_add_while_running(gpu_lib):
     """Members admitted while others are on the device finish with solo results."""
     from paper_2512_21164_amd.batch import Batch
