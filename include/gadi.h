@@ -218,6 +218,12 @@ gadi_status gadi_query(gadi_handle* h, int32_t wait, gadi_report* out, double* h
 /* ||A||_2 in use by the handle (given or estimated). */
 gadi_status gadi_get_norm(gadi_handle* h, double* normA);
 
+/* Tile shape the handle's step kernel runs with (host only, no device work):
+ * out[0] rows per wave of 3D tiles (1 in 2D), out[1] planes per chunk of the
+ * inner (u_s) tiling, out[2] planes per chunk of the FP64 tiling, out[3]
+ * blocks (tiles of four waves) of the larger tiling. */
+gadi_status gadi_get_tiling(gadi_handle* h, int32_t out[4]);
+
 /* Frees host state only; the caller frees the workspace afterwards. */
 gadi_status gadi_destroy(gadi_handle* h);
 

@@ -188,6 +188,23 @@ def backward_error(A, x, b, normA: float, extended: bool = False) -> float:
     return float(np.linalg.norm(r) / (normA * np.linalg.norm(x) + np.linalg.norm(b)))
 
 
+def backward_error_stencil(spec, x, b, normA: float) -> float:
+    """The backward error of Section 3 with the residual b - A x accumulated in
+    ``np.longdouble`` from the stencil's definition (``problems.apply_stencil``):
+    for grids too large to assemble A."""
+    from .problems import apply_stencil
+    cplx = spec.is_complex or np.iscomplexobj(x) or np.iscomplexobj(b)
+    dt = np.clongdouble if cplx else np.longdouble
+    xl = np.asarray(x).astype(dt)
+    r = np.asarray(b).astype(dt)
+    r -= apply_stencil(spec, xl)
+    nr = np.sqrt(np.sum(np.abs(r) ** 2))
+    del r
+    nx = np.sqrt(np.sum(np.abs(xl) ** 2))
+    nb = np.sqrt(np.sum(np.abs(np.asarray(b).astype(dt)) ** 2))
+    return float(nr / (np.longdouble(normA) * nx + nb))
+
+
 def _split(v):
     """Veltkamp's splitting: v = hi + lo exactly, each half with at most 26
     significant bits (float64, factor 2^27 + 1; no overflow for |v| < 1e300)."""

@@ -107,6 +107,36 @@ def assemble(spec: StencilSpec) -> sp.csr_matrix:
     return A
 
 
+def apply_stencil(spec: StencilSpec, x) -> np.ndarray:
+    """y = A x straight from the stencil's definition (see ``StencilSpec``), without a matrix.
+
+    The grid function is viewed as an array indexed (k, j, i) (x fastest) and
+    each neighbour term is a shifted slice, with zero values outside the grid.
+    The arithmetic is done in the dtype of x (e.g. ``np.longdouble`` for an
+    extended-precision residual), which is what makes this usable on grids
+    too large to assemble.
+    """
+    nx, ny, nz = spec.n
+    X = np.asarray(x).reshape(nz, ny, nx)
+    if spec.is_complex and not np.iscomplexobj(X):
+        X = X.astype(np.result_type(X.dtype, np.complex64))
+    Y = X * X.dtype.type(spec.center)
+    if spec.is_complex:
+        Y = Y + X * X.dtype.type(1j * spec.shift_im)
+    for d in range(spec.dim):
+        ax = 2 - d                        # axis of grid direction d in the (k, j, i) view
+        n = X.shape[ax]
+        if n < 2:
+            continue
+        head = [slice(None)] * 3
+        tail = [slice(None)] * 3
+        head[ax] = slice(0, n - 1)        # points that have a +d neighbour
+        tail[ax] = slice(1, n)            # points that have a -d neighbour
+        Y[tuple(head)] += X.dtype.type(spec.hi[d]) * X[tuple(tail)]
+        Y[tuple(tail)] += X.dtype.type(spec.lo[d]) * X[tuple(head)]
+    return Y.reshape(-1)
+
+
 def hss_split(A: sp.spmatrix):
     """Hermitian / skew-Hermitian splitting A = M + N (eq. (split), Section 3.1).
 

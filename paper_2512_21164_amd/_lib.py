@@ -72,6 +72,7 @@ SIGNATURES = [
     ("gadi_solve_async", C.c_int32, [_P, _P, _P]),
     ("gadi_query", C.c_int32, [_P, C.c_int32, _R, _D]),
     ("gadi_get_norm", C.c_int32, [_P, _D]),
+    ("gadi_get_tiling", C.c_int32, [_P, _I]),
     ("gadi_destroy", C.c_int32, [_P]),
     ("gadi_apply", C.c_int32, [_S, _P, _P, _P, C.c_int32]),
     ("gadi_residual", C.c_int32, [_S, _P, _P, _P, _P, C.c_int32]),

@@ -141,6 +141,14 @@ class Solver:
         _lib.check(self.lib.gadi_get_norm(self.handle, C.byref(v)), "gadi_get_norm")
         return v.value
 
+    @property
+    def tiling(self) -> dict:
+        """Tile shape of the handle's step kernel: rows per wave (ry), planes per chunk of the
+        inner and FP64 tilings, and blocks of the larger tiling."""
+        v = (C.c_int32 * 4)()
+        _lib.check(self.lib.gadi_get_tiling(self.handle, v), "gadi_get_tiling")
+        return {"ry": v[0], "chunk_inner": v[1], "chunk_fp64": v[2], "tiles": v[3]}
+
     def set_params(self, **params):
         p = make_params(**params)
         _lib.check(self.lib.gadi_set_params(self.handle, C.byref(p)), "gadi_set_params")

@@ -719,6 +719,15 @@ gadi_status gadi_get_norm(gadi_handle* h, double* normA) {
   return GADI_OK;
 }
 
+gadi_status gadi_get_tiling(gadi_handle* h, int32_t out[4]) {
+  if (!h || !out) return fail(GADI_ERR_INVALID_ARG, "null argument");
+  out[0] = h->lay.RY;
+  out[1] = h->lay.L;
+  out[2] = h->lay.Lo;
+  out[3] = h->lay.max_tiles;
+  return GADI_OK;
+}
+
 gadi_status gadi_destroy(gadi_handle* h) {
   if (!h) return GADI_OK;
   (void)hipStreamSynchronize(h->stream);
