@@ -10,9 +10,9 @@ inner solves is timed beside it.
 Default workload: 3D convection-diffusion, 512^3 interior grid (1.34e8
 unknowns), 7-point stencil, convection (10, 10, 10), omega = 1, x_true ~
 N(0, 1) seed 0, b = A x_true formed on the device, FP32 inner solves;
-alpha = 1.9307e-2 (the fourth of eight log-spaced values of [1e-3, 1]) and
-inner tolerance 1e-2 (from the paper's set 1e-2 .. 1e-6), the fastest pair of the
-parameter study for both inner precisions.  The 2D 4096^2 workload (--workload c2) remains
+alpha from the packaged Gaussian-process model (the data-driven initial alpha of
+Section 4.2: 1.756e-2 for this problem, close to the fastest alpha of a scan) and
+inner tolerance 1e-2 (from the paper's set 1e-2 .. 1e-6, the fastest here).  The 2D 4096^2 workload (--workload c2) remains
 available.
 
 Prints ONE JSON line (value = mixed-precision solves per second) with a
@@ -39,8 +39,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
-    # name: (dim, ng, beta, default alpha, default inner tolerance, description, oracle sample grid side)
-    "c3": (3, 512, 10.0, 1.9307e-2, 1e-2, "3D convection-diffusion 512^3 (1.34e8 unknowns), 7-point stencil", 128),
+    # name: (dim, ng, beta, default alpha ("gpr": the packaged regression model's prediction),
+    #        default inner tolerance, description, oracle sample grid side)
+    "c3": (3, 512, 10.0, "gpr", 1e-2, "3D convection-diffusion 512^3 (1.34e8 unknowns), 7-point stencil", 128),
     "c2": (2, 4096, 10.0, 7.1969e-3, 1e-2, "2D convection-diffusion 4096x4096 (1.68e7 unknowns), 5-point stencil",
            4096),
     "c1": (2, 64, 1.0, 0.5, 1e-3, "2D convection-diffusion 64x64 (4096 unknowns), 5-point stencil", 64),
@@ -69,9 +70,15 @@ def parse():
                     help="relative-residual tolerance of both inner solves (the paper picks it from 1e-2..1e-6); "
                          "default: the workload's (1e-2)")
     ap.add_argument("--max-outer", type=int, default=20000)
+    ap.add_argument("--fixed-inner", default=None,
+                    help="H,S: run exactly H CG and S CGNE iterations per sweep (with --tol 0 and --max-outer K a "
+                         "fixed phase sequence, for per-phase profiles)")
+    ap.add_argument("--normA", type=float, default=0.0, help="||A||_2 to use (0: estimate on the device)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64-inner solves (0: skip)")
     ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed FP64-inner solves before the timed ones")
     ap.add_argument("--tile-ry", type=int, default=0, help="3D rows per wave (0: library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate tile shapes first (gadi_autotune) and solve with the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps timed for the CPU baseline")
     ap.add_argument("--cpu-grid", type=int, default=0,
@@ -245,9 +252,9 @@ def main():
     inner_tol = itol0 if args.inner_tol is None else args.inner_tol
     pr = Problem.convection_diffusion(dim, ng, beta)
     alpha_source = "fixed"
-    if args.alpha is None:
+    if args.alpha is None and alpha0 != "gpr":
         alpha = alpha0
-    elif args.alpha == "gpr":
+    elif args.alpha is None or args.alpha == "gpr":
         from paper_2512_21164_amd.alpha_gpr import predict_alpha
         alpha = predict_alpha(pr, args.us)
         alpha_source = "gpr"
@@ -264,9 +271,13 @@ def main():
     nxt = torch.linalg.norm(xt)
 
     def run(us, steps, warmup):
+        fixed = {}
+        if args.fixed_inner:
+            fh, fs = (int(v) for v in args.fixed_inner.split(","))
+            fixed = dict(fixed_inner_h=fh, fixed_inner_s=fs, stag_window=0, div_factor=0.0)
         s = Solver(pr, alpha=alpha, omega=1.0, u_s=us, u_r=args.u_r, tol=args.tol, max_outer=args.max_outer,
                    inner_tol_h=inner_tol, inner_tol_s=inner_tol, max_restarts=args.max_restarts,
-                   tile_ry=args.tile_ry)
+                   tile_ry=args.tile_ry, autotune=args.autotune, normA=args.normA, **fixed)
         tiling = s.tiling
         reps = []
         x = torch.zeros_like(b)

@@ -110,9 +110,11 @@ typedef struct {
   int32_t fixed_inner_s;
   double normA;            /* > 0: use this ||A||_2; 0: estimate at gadi_create           */
   int32_t norm_iters;      /* power iterations for the estimate (default 100)             */
-  int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0: library default (4 for
-                              FP64 / FP32 inner solves, 2 for BF16, 1 for complex)        */
-  int32_t tile_chunk;      /* planes per tile along the marching axis; 0: default          */
+  int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0 (with tile_chunk 0): the
+                              shape gadi_autotune chose for this class, else the library
+                              default (4 for FP64 / FP32 inner solves, 2 for BF16, 1 for
+                              complex)                                                    */
+  int32_t tile_chunk;      /* planes per tile along the marching axis; 0: as tile_ry      */
   int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
                               4.3, step 3); 0 (default): none                            */
   double safeguard_tau;    /* > 0: before the solve, raise alpha until
@@ -308,19 +310,27 @@ gadi_status gadi_batch_remove(gadi_batch* b, int32_t slot, gadi_report* out, dou
 gadi_status gadi_batch_destroy(gadi_batch* b);
 
 /* ---- autotuning -----------------------------------------------------------
- * Choose the tile shape of the step kernels (rows per wave in 3D, planes per
- * chunk along the marching axis) for this stencil's shape and precision by
- * timing candidate shapes on the device: for each one a handle is created in
- * the caller's workspace (ws_bytes must cover the largest candidate layout;
- * gadi_workspace_bytes with tile_chunk = 2 is an upper bound), the state
- * machine is armed with d_b / d_x (read only; x is not written) and a run of
- * CG iterations on H is timed with hipEvents.  Returns the fastest shape in
- * *ry, *chunk and its time per CG iteration in *best_us.  Results are cached
- * per (dimension, grid, precision) for the process and, when the
- * environment variable GADI_TUNE_CACHE names a file, across processes. */
+ * Choose the tile shape of the step kernels (rows per wave in 3D: 1, 2 or 4;
+ * planes per chunk of the inner tiling: half, once or twice the length that
+ * fills the device in one round) for this stencil's kernel class (dimension,
+ * real / complex, u_s, u_r) and size class (floor(log2 n)) by timing each
+ * candidate on the device: a handle is created in the caller's workspace
+ * (ws_bytes must cover the largest candidate layout; gadi_workspace_bytes with
+ * tile_ry = 1 and tile_chunk = 2 is an upper bound), the state machine is armed
+ * with d_b / d_x (read only; x is not written) and whole sweeps (every phase:
+ * the outer update and residual, 8 CG and 2 CGNE iterations) are timed with
+ * hipEvents.  Returns the fastest shape for this grid in *ry, *chunk and its
+ * time per sweep in *best_us.  The choice is kept for the class for the
+ * process and, when the environment variable GADI_TUNE_CACHE names a file,
+ * appended to it and read back by later processes; a class that already has
+ * a choice is not timed again (*best_us = -1).  Every handle created
+ * afterwards with tile_ry = tile_chunk = 0 (gadi_create, batches, the
+ * allocation-free solve) runs with the shape chosen for its class; create
+ * workspaces after tuning, since the shape changes the layout. */
 gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* p, void* hip_stream,
                           void* d_workspace, size_t ws_bytes, const void* d_b, void* d_x,
                           int32_t* ry, int32_t* chunk, double* best_us);
+
 
 #ifdef __cplusplus
 }

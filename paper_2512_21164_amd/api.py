@@ -115,9 +115,15 @@ def workspace_bytes(problem: Problem, params: _lib.gadi_params) -> int:
 class Solver:
     """A gadi_handle with its workspace (a torch uint8 tensor on the device)."""
 
-    def __init__(self, problem: Problem, stream=None, device="cuda", workspace=None, **params):
+    def __init__(self, problem: Problem, stream=None, device="cuda", workspace=None, autotune: bool = False,
+                 **params):
+        """autotune: before sizing the workspace, let the library time the tile shapes of this
+        problem's class (once per class and process, see ``autotune``) unless tile_ry or
+        tile_chunk is given."""
         import torch
         self.lib = _lib.load()
+        if autotune and not params.get("tile_ry") and not params.get("tile_chunk"):
+            autotune_class(problem, stream=stream, device=device, **params)
         self.problem = problem
         self.params = make_params(**params)
         self.stream = stream
@@ -245,7 +251,9 @@ def residual(problem: Problem, b, x, u_r="f64", stream=None):
 
 
 def autotune(problem: Problem, b, x, stream=None, **params):
-    """Pick (tile_ry, tile_chunk) for this problem by timing; returns (ry, chunk, us_per_cg_iteration)."""
+    """Choose (tile_ry, tile_chunk) for this problem's class by timing whole sweeps on the device
+    (gadi_autotune); returns (ry, chunk, microseconds per sweep, or -1 when the class was tuned
+    already).  Handles created afterwards without an explicit tile shape use the choice."""
     import torch
     lib = _lib.load()
     p = make_params(**params)
@@ -257,8 +265,19 @@ def autotune(problem: Problem, b, x, stream=None, **params):
                                  C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes), C.c_void_p(b.data_ptr()),
                                  C.c_void_p(x.data_ptr()), C.byref(ry), C.byref(ch), C.byref(us)),
                "gadi_autotune")
+    torch.cuda.current_stream(b.device).synchronize() if stream is None else stream.synchronize()
     del ws
     return ry.value, ch.value, us.value
 
 
-__all__ = ["Problem", "Solver", "make_params", "apply", "autotune", "workspace_bytes"]
+def autotune_class(problem: Problem, stream=None, device="cuda", **params):
+    """Tune the tile shape of this problem's class on a synthetic right-hand side b = A 1
+    (nothing is read from or written to caller data); see ``autotune``."""
+    import torch
+    ones = torch.ones(problem.size, dtype=_dtype(problem), device=device)
+    b = apply(problem, ones, stream=stream)
+    x = torch.zeros_like(b)
+    return autotune(problem, b, x, stream=stream, **params)
+
+
+__all__ = ["Problem", "Solver", "make_params", "apply", "autotune", "autotune_class", "workspace_bytes"]

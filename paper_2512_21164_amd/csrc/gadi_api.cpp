@@ -214,7 +214,52 @@ int default_ry(int us, int cplx) {
   return us == US_BF16 ? 2 : 4;
 }
 
-Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
+// Tile shapes chosen by the autotuner, per kernel class and size class:
+// rows per wave and the inner chunk length as a multiple of the one-round
+// default.  Handles created without an explicit tile shape use the entry of
+// their class when there is one (see gadi_autotune).
+struct TunedShape { int ry; double chunk_factor; };
+std::mutex g_tune_mu;
+std::map<std::string, TunedShape> g_tune_cache;
+bool g_tune_file_read = false;
+
+std::string tune_class_key(const gadi_stencil* st, const gadi_params* p) {
+  const double n = (double)st->n[0] * (double)st->n[1] * (double)st->n[2];
+  const int size_class = (int)std::floor(std::log2(std::max(1.0, n)));
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "d%d_c%d_u%d_x%d_n%d", st->dim, st->is_complex ? 1 : 0, p->u_s,
+                p->u_r == GADI_F64X2 ? 1 : 0, size_class);
+  return buf;
+}
+
+void load_tune_file_locked() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* f = std::getenv("GADI_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "r");
+  if (!fp) return;
+  char key[96];
+  int ry = 0;
+  double fac = 0.0;
+  while (std::fscanf(fp, "%95s %d %lf", key, &ry, &fac) == 3)
+    if ((ry == 1 || ry == 2 || ry == 4) && fac > 0.0 && fac <= 64.0) g_tune_cache[key] = {ry, fac};
+  std::fclose(fp);
+}
+
+bool tuned_shape(const gadi_stencil* st, const gadi_params* p, TunedShape* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_file_locked();
+  auto it = g_tune_cache.find(tune_class_key(st, p));
+  if (it == g_tune_cache.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// use_tuned: consult the autotuner's cache when p leaves the tile shape to the library
+Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned = true) {
+  TunedShape tuned{0, 0.0};
+  const bool have_tuned = use_tuned && p->tile_ry == 0 && p->tile_chunk == 0 && tuned_shape(st, p, &tuned);
   Layout l{};
   l.dim = st->dim; l.cplx = st->is_complex ? 1 : 0; l.us = p->u_s;
   l.xr = p->u_r == GADI_F64X2 ? 1 : 0;
@@ -226,7 +271,7 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
     l.ny_plane = 1; l.nm = l.ny; l.sy = l.P; l.sm = l.P; l.RY = 1;
   } else {
     l.ny_plane = l.ny; l.nm = l.nz; l.sy = l.P; l.sm = l.P * l.ny;
-    l.RY = p->tile_ry ? p->tile_ry : default_ry(l.us, l.cplx);
+    l.RY = p->tile_ry ? p->tile_ry : (have_tuned ? tuned.ry : default_ry(l.us, l.cplx));
   }
   l.nwy = (l.dim == 2) ? 1 : (l.ny_plane + l.RY - 1) / l.RY;
   // elements per lane of the inner phases (16-byte lane accesses)
@@ -245,6 +290,8 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p) {
   };
   const int vo = l.cplx ? 1 : 2;
   l.L = p->tile_chunk > 0 ? p->tile_chunk : one_round(vi);
+  if (have_tuned)
+    l.L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(tuned.chunk_factor * one_round(vi))));
   l.Lo = one_round(vo);
   l.ti = make_tiling(l, vi, l.L);
   l.to = make_tiling(l, vo, l.Lo);
@@ -1060,49 +1107,36 @@ gadi_status gadi_batch_destroy(gadi_batch* b) {
 // ============================================================== autotuning
 namespace {
 
-std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;
-
-std::string tune_key(const gadi_stencil* st, const gadi_params* p) {
-  char buf[128];
-  std::snprintf(buf, sizeof(buf), "d%d_c%d_u%d_%lldx%lldx%lld", st->dim, st->is_complex ? 1 : 0, p->u_s,
-                (long long)st->n[0], (long long)st->n[1], (long long)st->n[2]);
-  return buf;
-}
-
-void load_tune_file() {
-  const char* f = std::getenv("GADI_TUNE_CACHE");
-  if (!f) return;
-  FILE* fp = std::fopen(f, "r");
-  if (!fp) return;
-  char key[128];
-  int ry, L;
-  while (std::fscanf(fp, "%127s %d %d", key, &ry, &L) == 3) g_tune_cache[key] = {ry, L};
-  std::fclose(fp);
-}
-
-void save_tune_entry(const std::string& key, int ry, int L) {
+void save_tune_entry(const std::string& key, int ry, double factor) {
   const char* f = std::getenv("GADI_TUNE_CACHE");
   if (!f) return;
   FILE* fp = std::fopen(f, "a");
   if (!fp) return;
-  std::fprintf(fp, "%s %d %d\n", key.c_str(), ry, L);
+  std::fprintf(fp, "%s %d %.6g\n", key.c_str(), ry, factor);
   std::fclose(fp);
 }
 
-// Time CG iterations on H for one tile shape; returns microseconds per iteration.
+// Device steps of one sweep in the tuner's fixed-count solve: OUTER, then
+// (H1 H2) per CG iteration, then S0 S2 (S1 S2)^(CGNE iterations - 1).
+constexpr int kTuneCG = 8, kTuneCGNE = 2;
+int tune_steps_per_sweep(int cplx) { return 1 + 2 * kTuneCG + (cplx ? 0 : 2 * kTuneCGNE); }
+
+// Time whole sweeps (every phase, 8 CG and 2 CGNE iterations each) with one
+// tile shape; returns microseconds per sweep.
 gadi_status time_shape(const gadi_stencil* st, const gadi_params* base, int ry, int L, hipStream_t stream, void* ws,
-                       size_t ws_bytes, const void* b, void* x, double* us_per_it) {
+                       size_t ws_bytes, const void* b, void* x, double* us_per_sweep) {
   gadi_params q = *base;
   q.tile_ry = ry;
   q.tile_chunk = L;
   q.normA = 1.0;
-  q.max_outer = 1;
-  q.fixed_inner_h = 1 << 30;
-  q.max_inner_h = 1 << 30;
+  q.max_outer = 4;          // more than the sweeps run here: the machine stays in its sweeps
+  q.fixed_inner_h = kTuneCG;
+  q.fixed_inner_s = kTuneCGNE;
   q.tol = 0.0;
   q.stag_window = 0;
   q.div_factor = 0.0;
+  q.max_restarts = 0;
+  q.safeguard_tau = 0.0;
   size_t need = 0;
   gadi_status s = gadi_workspace_bytes(st, &q, &need);
   if (s != GADI_OK) return s;
@@ -1110,23 +1144,23 @@ gadi_status time_shape(const gadi_stencil* st, const gadi_params* base, int ry, 
   gadi_handle* h = nullptr;
   s = gadi_create(st, &q, stream, ws, ws_bytes, &h);
   if (s != GADI_OK) return s;
-  const int warm = 8, meas = 40;
+  const int per = tune_steps_per_sweep(h->lay.cplx), warm = 1, meas = 2;   // warm + meas < q.max_outer
   s = start_solve(h, b, x);
-  if (s == GADI_OK) s = launch_steps(h, 2 + warm);           // IMPORT, OUTER, warm-up CG steps
-  hipEvent_t e0 = h->ev0, e1 = h->ev1;
+  if (s == GADI_OK) s = launch_steps(h, 1 + warm * per);           // IMPORT and a warm-up sweep
+  hipEvent_t e0 = h->ec0, e1 = h->ec1;
   if (s == GADI_OK && hipEventRecord(e0, stream) != hipSuccess) s = fail(GADI_ERR_HIP, "event");
-  if (s == GADI_OK) s = launch_steps(h, 2 * meas);
+  if (s == GADI_OK) s = launch_steps(h, meas * per);
   if (s == GADI_OK && hipEventRecord(e1, stream) != hipSuccess) s = fail(GADI_ERR_HIP, "event");
   if (s == GADI_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(GADI_ERR_HIP, "event sync");
   if (s == GADI_OK) s = read_ctl(h);
-  if (s == GADI_OK && !(h->h_ctl->phase == PH_H1 || h->h_ctl->phase == PH_H2))
-    s = fail(GADI_ERR_STATE, "autotune: state machine left the CG phase");
+  if (s == GADI_OK && !(h->h_ctl->phase == PH_OUTER && h->h_ctl->k == warm + meas))
+    s = fail(GADI_ERR_STATE, "autotune: the state machine is not at the start of a sweep after the timed steps");
   float ms = 0.f;
   if (s == GADI_OK) (void)hipEventElapsedTime(&ms, e0, e1);
   h->running = 0;
   gadi_destroy(h);
   if (s != GADI_OK) return s;
-  *us_per_it = 1000.0 * ms / meas;
+  *us_per_sweep = 1000.0 * ms / meas;
   return GADI_OK;
 }
 
@@ -1138,44 +1172,48 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
   if (!ry || !chunk || !d_b || !d_x) return fail(GADI_ERR_INVALID_ARG, "null argument");
   gadi_status s = validate(st, p);
   if (s != GADI_OK) return s;
-  const std::string key = tune_key(st, p);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (g_tune_cache.empty()) load_tune_file();
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      *ry = it->second.first;
-      *chunk = it->second.second;
-      if (best_us) *best_us = -1.0;
-      return GADI_OK;
-    }
+  const std::string key = tune_class_key(st, p);
+  TunedShape known{0, 0.0};
+  if (tuned_shape(st, p, &known)) {
+    // this class is tuned already (in this process or in the GADI_TUNE_CACHE file)
+    gadi_params q = *p;
+    q.tile_ry = 0;
+    q.tile_chunk = 0;
+    const Layout l = make_layout(st, &q, true);
+    *ry = l.RY;
+    *chunk = l.L;
+    if (best_us) *best_us = -1.0;
+    return GADI_OK;
   }
-  std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2} : std::vector<int>{1};
-  double best = 1e300;
+  // candidates: every rows-per-wave value (3D) with the one-round chunk, its half and its double
+  const std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
+  const double factors[3] = {0.5, 1.0, 2.0};
+  double best = 1e300, bfac = 1.0;
   int bry = 0, bL = 0;
+  std::vector<std::pair<int, int>> seen;
   for (int r : rys) {
-    // candidates: the one-round chunk of this shape, its half and double, and fixed lengths
     gadi_params q = *p;
     q.tile_ry = r;
     q.tile_chunk = 0;
-    const int Ldef = make_layout(st, &q).L;
-    std::vector<int> Ls{std::max(2, Ldef / 2), Ldef, 2 * Ldef, 8, 16, 32, 64};
-    std::sort(Ls.begin(), Ls.end());
-    Ls.erase(std::unique(Ls.begin(), Ls.end()), Ls.end());
-    for (int L : Ls) {
+    const int Ldef = make_layout(st, &q, false).L;
+    for (double f : factors) {
+      const int L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(f * Ldef)));
+      if (std::find(seen.begin(), seen.end(), std::make_pair(r, L)) != seen.end()) continue;
+      seen.emplace_back(r, L);
       double us = 0.0;
       s = time_shape(st, p, r, L, static_cast<hipStream_t>(hip_stream), d_workspace, ws_bytes, d_b, d_x, &us);
       if (s != GADI_OK) return s;
       if (std::getenv("GADI_TUNE_VERBOSE"))
-        std::fprintf(stderr, "gadi_autotune %s ry=%d chunk=%d: %.2f us per CG iteration\n", key.c_str(), r, L, us);
-      if (us < best) { best = us; bry = r; bL = L; }
+        std::fprintf(stderr, "gadi_autotune %s ry=%d chunk=%d: %.2f us per sweep\n", key.c_str(), r, L, us);
+      if (us < best) { best = us; bry = r; bL = L; bfac = (double)L / (double)Ldef; }
     }
   }
   *ry = bry;
   *chunk = bL;
   if (best_us) *best_us = best;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = {bry, bL};
-  save_tune_entry(key, bry, bL);
+  load_tune_file_locked();
+  g_tune_cache[key] = {bry, bfac};
+  save_tune_entry(key, bry, bfac);
   return GADI_OK;
 }

@@ -70,3 +70,66 @@ def test_an_extra_arrival_stalls_a_later_launch():
     assert run_launch(list(range(17)), 17, ctr) != []
     assert ctr != [0] * (1 + GROUPS)
     assert run_launch(list(range(9)), 9, ctr) == []
+
+
+def _launch_schedule(lim, rng):
+    """Random start / arrival times of the lim slots of one launch (start before arrival)."""
+    ev = []
+    for sl in range(lim):
+        a, b = sorted(rng.random() for _ in range(2))
+        ev.append((a, "start", sl))
+        ev.append((b, "arrive", sl))
+    ev.sort()
+    return ev
+
+
+def _single_system_launch(ev, ntiles, phase0, lim, count_slots):
+    """One launch of a single system whose two tilings have ntiles[phase] tiles.
+
+    Each slot reads the phase when it starts.  count_slots=False: the rule before the
+    fix, a slot with no tile of the phase it read leaves without a ticket and the
+    ticket target is that phase's tile count.  count_slots=True: every slot takes a
+    ticket and the target is the phase-independent slot count lim.  Returns (slots
+    that read a phase other than phase0, number of finalizes, tickets taken toward a
+    phase other than phase0)."""
+    phase = phase0
+    seen = {}
+    count = 0
+    finals = 0
+    stray = 0
+    for _, kind, sl in ev:
+        if kind == "start":
+            seen[sl] = phase
+            continue
+        ph = seen[sl]
+        if not count_slots and sl >= ntiles[ph]:
+            continue
+        if ph != phase0:
+            stray += 1
+            continue
+        count += 1
+        target = lim if count_slots else ntiles[phase0]
+        if count == target:
+            finals += 1
+            phase = 1 - phase0               # the finalize sets the next phase
+    late = sum(1 for ph in seen.values() if ph != phase0)
+    return late, finals, stray
+
+
+def test_single_system_late_slot_reads_the_next_phase_only_with_the_tile_count_ticket():
+    """A single system whose inner tiling has 3 tiles and whose FP64 tiling has 5 runs
+    on lim = 8 slots.  With tickets counting the phase's tiles, a slot that starts after
+    the finalize reads the next phase, runs one of its tiles inside the launch and takes
+    a ticket toward it (the offset that stalls a later launch, as above).  With tickets
+    counting every slot, the finalize is the last event of the launch."""
+    rng = random.Random(5)
+    ntiles, lim = {0: 3, 1: 5}, 8
+    strays_old = 0
+    for _ in range(2000):
+        ev = _launch_schedule(lim, rng)
+        late, finals, stray = _single_system_launch(ev, ntiles, 0, lim, count_slots=False)
+        assert finals == 1
+        strays_old += stray
+        late, finals, stray = _single_system_launch(ev, ntiles, 0, lim, count_slots=True)
+        assert (late, finals, stray) == (0, 1, 0)
+    assert strays_old > 0
