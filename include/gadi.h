@@ -331,6 +331,29 @@ gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* p, void* hi
                           void* d_workspace, size_t ws_bytes, const void* d_b, void* d_x,
                           int32_t* ry, int32_t* chunk, double* best_us);
 
+/* ---- allocation-free solve -------------------------------------------------
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid it, set-ups that
+ * record their other work into HIP graphs).  One whole solve, equivalent to
+ * gadi_create + gadi_solve + gadi_destroy with the same stencil and
+ * parameters (same kernels, same tile shape, same results), whose workspace
+ * is a static device array of GADI_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library (one per GPU, created when the library's code is loaded on that GPU
+ * and held until the process ends) instead of caller memory.  The call makes
+ * no hipMalloc / hipFree, no pinned host allocation and no event.  The caller
+ * passes b and x (x^(0) in, result out) as for gadi_solve, on the current
+ * device.  A problem whose workspace (gadi_workspace_bytes) exceeds the limit
+ * returns GADI_ERR_CAPACITY before any device work; with the default tile
+ * shapes 64 MiB holds about 1.6e6 real unknowns with FP32 inner solves, 2.0e6
+ * with BF16 and 1.1e6 with FP64.  All calls on one GPU share its array and
+ * each call clears the part it uses before solving: calls that overlap on
+ * one GPU (two threads, or two streams without ordering) race and corrupt
+ * each other, so the caller serializes them.  The call synchronizes the
+ * stream between launch chunks, so it cannot itself be captured in a graph.
+ * The report's ms and kernel_ms are host-clock times of the call. */
+#define GADI_NOALLOC_SCRATCH_BYTES (64u << 20)
+gadi_status gadi_solve_noalloc(const gadi_stencil* st, const gadi_params* p, void* hip_stream,
+                               const void* d_b, void* d_x, gadi_report* out, double* h_history);
 
 #ifdef __cplusplus
 }

@@ -88,7 +88,10 @@ SIGNATURES = [
     ("gadi_batch_remove", C.c_int32, [_P, C.c_int32, _R, _D]),
     ("gadi_batch_destroy", C.c_int32, [_P]),
     ("gadi_autotune", C.c_int32, [_S, _PP, _P, _P, C.c_size_t, _P, _P, _I, _I, _D]),
+    ("gadi_solve_noalloc", C.c_int32, [_S, _PP, _P, _P, _P, _R, _D]),
 ]
+# device bytes of the allocation-free solve's static workspace (GADI_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 

@@ -250,6 +250,31 @@ def residual(problem: Problem, b, x, u_r="f64", stream=None):
     return r
 
 
+def solve_noalloc(problem: Problem, b, x=None, history: bool = False, stream=None, **params):
+    """One solve through gadi_solve_noalloc: the library's static device workspace, no allocation
+    by the library (x is allocated here only when not given).  Returns (x, report[, history])."""
+    import torch
+    lib = _lib.load()
+    if x is None:
+        x = torch.zeros_like(b)
+    _check_dense(problem, b, x)
+    p = make_params(**params)
+    rep = _lib.gadi_report()
+    buf = ptr = None
+    if history:
+        buf = np.zeros(4 * (int(p.max_outer) + 1), dtype=np.float64)
+        ptr = buf.ctypes.data_as(C.POINTER(C.c_double))
+    st = _lib.check(lib.gadi_solve_noalloc(C.byref(problem.c_struct()), C.byref(p),
+                                           C.c_void_p(_stream_handle(stream)), C.c_void_p(b.data_ptr()),
+                                           C.c_void_p(x.data_ptr()), C.byref(rep), ptr), "gadi_solve_noalloc")
+    out = rep.as_dict()
+    out["status_name"] = lib.gadi_status_string(st).decode()
+    if history:
+        k = int(rep.attempt_outer) + 1
+        return x, out, buf[: 4 * k].reshape(k, 4)
+    return x, out
+
+
 def autotune(problem: Problem, b, x, stream=None, **params):
     """Choose (tile_ry, tile_chunk) for this problem's class by timing whole sweeps on the device
     (gadi_autotune); returns (ry, chunk, microseconds per sweep, or -1 when the class was tuned
@@ -280,4 +305,5 @@ def autotune_class(problem: Problem, stream=None, device="cuda", **params):
     return autotune(problem, b, x, stream=stream, **params)
 
 
-__all__ = ["Problem", "Solver", "make_params", "apply", "autotune", "autotune_class", "workspace_bytes"]
+__all__ = ["Problem", "Solver", "make_params", "apply", "autotune", "autotune_class", "solve_noalloc",
+           "workspace_bytes"]

@@ -388,9 +388,11 @@ struct gadi_handle {
   BatchTable* d_table;
   GadiCtl* h_ctl;        // pinned readback buffer
   double normA;
-  hipEvent_t ev0, ev1;
-  hipEvent_t ec0, ec1;   // around each chunk of step launches
+  hipEvent_t ev0, ev1;   // around the solve (null: timed on the host instead)
+  hipEvent_t ec0, ec1;   // around each chunk of step launches (null: not timed)
   double kernel_ms;
+  std::chrono::steady_clock::time_point t_start;   // host clock at the start of the solve
+  double host_ms;        // host-timed solve (handles without events)
   // asynchronous solve
   int running;
   int chunk;
@@ -435,14 +437,14 @@ int64_t step_bound(const gadi_params& p, int cplx) {
 
 gadi_status run_to(gadi_handle* h, int target_phase, bool wait, int64_t bound) {
   for (;;) {
-    HIP_TRY(hipEventRecord(h->ec0, h->stream));
+    if (h->ec0) HIP_TRY(hipEventRecord(h->ec0, h->stream));
     gadi_status s = launch_steps(h, h->chunk);
     if (s != GADI_OK) return s;
-    HIP_TRY(hipEventRecord(h->ec1, h->stream));
+    if (h->ec1) HIP_TRY(hipEventRecord(h->ec1, h->stream));
     s = read_ctl(h);
     if (s != GADI_OK) return s;
     float cms = 0.f;
-    if (hipEventElapsedTime(&cms, h->ec0, h->ec1) == hipSuccess) h->kernel_ms += cms;
+    if (h->ec0 && hipEventElapsedTime(&cms, h->ec0, h->ec1) == hipSuccess) h->kernel_ms += cms;
     if (h->h_ctl->phase == target_phase) return GADI_OK;
     if (h->steps > bound) return fail(GADI_ERR_STATE, "device state machine did not finish within its step bound");
     h->chunk = std::min(h->chunk * 2, 256);
@@ -460,10 +462,15 @@ void fill_report(gadi_handle* h, gadi_report* out) {
   out->relres = c.relres;
   out->normA = c.normA;
   out->normb = c.normb;
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) ms = -1.f;
-  out->ms = ms;
-  out->kernel_ms = h->kernel_ms;
+  if (h->ev0) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) ms = -1.f;
+    out->ms = ms;
+    out->kernel_ms = h->kernel_ms;
+  } else {
+    out->ms = h->host_ms;
+    out->kernel_ms = h->host_ms;
+  }
   out->status = c.status;
   out->steps = (int32_t)std::min<int64_t>(h->acc_steps + h->steps, INT32_MAX);
   out->alpha = h->alpha_cur;
@@ -506,7 +513,8 @@ gadi_status start_solve(gadi_handle* h, const void* b, void* x) {
   h->restarts = 0;
   h->acc_outer = h->acc_inner_h = h->acc_inner_s = h->acc_steps = 0;
   h->kernel_ms = 0.0;
-  HIP_TRY(hipEventRecord(h->ev0, h->stream));
+  h->t_start = std::chrono::steady_clock::now();
+  if (h->ev0) HIP_TRY(hipEventRecord(h->ev0, h->stream));
   s = arm_attempt(h, alpha, h->p.max_outer);
   if (s != GADI_OK) return s;
   h->running = 1;
@@ -542,8 +550,13 @@ gadi_status restart_solve(gadi_handle* h) {
 }
 
 gadi_status finish_solve(gadi_handle* h, gadi_report* out, double* hist) {
-  HIP_TRY(hipEventRecord(h->ev1, h->stream));
-  HIP_TRY(hipEventSynchronize(h->ev1));
+  if (h->ev1) {
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    HIP_TRY(hipEventSynchronize(h->ev1));
+  } else {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  h->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h->t_start).count();
   h->running = 0;
   fill_report(h, out);
   gadi_status s = copy_history(h, hist);
@@ -551,6 +564,92 @@ gadi_status finish_solve(gadi_handle* h, gadi_report* out, double* hist) {
   return h->h_ctl->status;
 }
 
+// Lay a handle out over its workspace: descriptor, the single-system table,
+// a zeroed workspace, and ||A||_2 (given, or estimated by power iteration).
+// h->h_ctl must point at host memory for the control-block readback; the
+// events are optional (null: no device timing).  zero_fill clears the
+// workspace with a kernel on the stream (null: hipMemsetAsync).
+gadi_status setup_handle(gadi_handle* h, const gadi_stencil* st, const gadi_params* p, hipStream_t stream, char* ws,
+                         size_t ws_bytes, const Layout& l,
+                         hipError_t (*zero_fill)(void*, size_t, hipStream_t)) {
+  h->st = *st; h->p = *p;
+  h->stream = stream;
+  h->ws = ws;
+  h->ws_bytes = ws_bytes;
+  h->lay = l;
+  h->d_desc = reinterpret_cast<GadiDesc*>(h->ws + l.o_desc);
+  h->d_ctl = reinterpret_cast<GadiCtl*>(h->ws + l.o_ctl);
+  h->d_table = reinterpret_cast<BatchTable*>(h->ws + l.o_table);
+  fill_desc(h->hdesc, l, st, p, h->ws);
+  // single-system table: desc pointer and tile prefix live right after the table header
+  char* tb = h->ws + l.o_table;
+  BatchTable t{};
+  t.nsys = 1;
+  t.total_tiles = l.max_tiles;
+  t.slots = (l.max_tiles + 7) / 8 * 8;
+  t.desc = reinterpret_cast<GadiDesc**>(tb + sizeof(BatchTable));
+  t.tile_start = reinterpret_cast<int32_t*>(tb + sizeof(BatchTable) + sizeof(GadiDesc*));
+  char tbuf[sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t)];
+  std::memcpy(tbuf, &t, sizeof(t));
+  std::memcpy(tbuf + sizeof(BatchTable), &h->d_desc, sizeof(GadiDesc*));
+  int32_t ts[2] = {0, l.max_tiles};
+  std::memcpy(tbuf + sizeof(BatchTable) + sizeof(GadiDesc*), ts, sizeof(ts));
+  hipError_t e = zero_fill ? zero_fill(h->ws, l.total, h->stream) : hipMemsetAsync(h->ws, 0, l.total, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(GadiDesc), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(tb, tbuf, sizeof(tbuf), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("workspace init: ") + hipGetErrorString(e));
+  if (p->normA > 0.0) {
+    h->normA = p->normA;
+    e = launch_set_norm(h->d_ctl, p->normA, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("set norm: ") + hipGetErrorString(e));
+  } else {
+    // power iteration on A^H A from a checkerboard start (2 steps per iteration)
+    e = launch_set_phase(h->d_ctl, PH_NORM_A, p->norm_iters, 1.0 / std::sqrt((double)l.n), h->stream);
+    if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("set phase: ") + hipGetErrorString(e));
+    h->steps = 0;
+    gadi_status s = launch_steps(h, 2 * p->norm_iters);
+    if (s == GADI_OK) s = read_ctl(h);
+    if (s != GADI_OK) return s;
+    if (h->h_ctl->phase != PH_IDLE) return fail(GADI_ERR_STATE, "norm estimation did not finish");
+    h->normA = h->h_ctl->normA;
+  }
+  return GADI_OK;
+}
+
+}  // namespace
+
+extern "C" gadi_status gadi_solve(gadi_handle* h, const void* d_b, void* d_x, gadi_report* out, double* h_history);
+
+namespace gadi {
+
+// One whole solve (set-up, Algorithm 1, end) over device memory the caller
+// provides, allocating nothing: the handle and the host copy of the control
+// block live on this function's stack and no events are created (the report
+// carries host-clock times).
+int32_t solve_in_place(const gadi_stencil* st, const gadi_params* p, void* hip_stream, void* ws, size_t ws_cap,
+                       hipError_t (*zero_fill)(void*, size_t, hipStream_t), const void* d_b, void* d_x,
+                       gadi_report* out, double* h_history) {
+  gadi_status s = validate(st, p);
+  if (s != GADI_OK) return s;
+  if (!d_b || !d_x) return fail(GADI_ERR_INVALID_ARG, "null b or x");
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(GADI_ERR_WORKSPACE, "bad scratch address");
+  const Layout l = make_layout(st, p);
+  if (l.total > ws_cap)
+    return fail(GADI_ERR_CAPACITY, "problem needs " + std::to_string(l.total) + " bytes of device workspace; "
+                                   "the allocation-free solve has " + std::to_string(ws_cap));
+  gadi_handle h{};
+  GadiCtl ctl{};
+  h.h_ctl = &ctl;
+  s = setup_handle(&h, st, p, static_cast<hipStream_t>(hip_stream), static_cast<char*>(ws), ws_cap, l, zero_fill);
+  if (s != GADI_OK) return s;
+  return gadi_solve(&h, d_b, d_x, out, h_history);
+}
+
+}  // namespace gadi
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -629,16 +728,13 @@ gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_
   if (ws_bytes < l.total)
     return fail(GADI_ERR_WORKSPACE, "workspace too small: need " + std::to_string(l.total) + " bytes");
   gadi_handle* h = new gadi_handle();
-  h->st = *st; h->p = *p;
-  h->stream = static_cast<hipStream_t>(hip_stream);
-  h->ws = static_cast<char*>(d_workspace);
-  h->ws_bytes = ws_bytes;
-  h->lay = l;
-  h->d_desc = reinterpret_cast<GadiDesc*>(h->ws + l.o_desc);
-  h->d_ctl = reinterpret_cast<GadiCtl*>(h->ws + l.o_ctl);
-  h->d_table = reinterpret_cast<BatchTable*>(h->ws + l.o_table);
-  fill_desc(h->hdesc, l, st, p, h->ws);
-  auto cleanup = [&](gadi_status e) { if (h->h_ctl) (void)hipHostFree(h->h_ctl); delete h; return e; };
+  auto cleanup = [&](gadi_status e) {
+    if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+    for (hipEvent_t ev : {h->ev0, h->ev1, h->ec0, h->ec1})
+      if (ev) (void)hipEventDestroy(ev);
+    delete h;
+    return e;
+  };
   if (hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(GadiCtl), hipHostMallocDefault) != hipSuccess) {
     h->h_ctl = nullptr;
     return cleanup(fail(GADI_ERR_HIP, "pinned host buffer"));
@@ -646,40 +742,9 @@ gadi_status gadi_create(const gadi_stencil* st, const gadi_params* p, void* hip_
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
       hipEventCreate(&h->ec0) != hipSuccess || hipEventCreate(&h->ec1) != hipSuccess)
     return cleanup(fail(GADI_ERR_HIP, "event create"));
-  // single-system table: desc pointer and tile prefix live right after the table header
-  char* tb = h->ws + l.o_table;
-  BatchTable t{};
-  t.nsys = 1;
-  t.total_tiles = l.max_tiles;
-  t.slots = (l.max_tiles + 7) / 8 * 8;
-  t.desc = reinterpret_cast<GadiDesc**>(tb + sizeof(BatchTable));
-  t.tile_start = reinterpret_cast<int32_t*>(tb + sizeof(BatchTable) + sizeof(GadiDesc*));
-  std::vector<char> tbuf(sizeof(BatchTable) + sizeof(GadiDesc*) + 2 * sizeof(int32_t));
-  std::memcpy(tbuf.data(), &t, sizeof(t));
-  std::memcpy(tbuf.data() + sizeof(BatchTable), &h->d_desc, sizeof(GadiDesc*));
-  int32_t ts[2] = {0, l.max_tiles};
-  std::memcpy(tbuf.data() + sizeof(BatchTable) + sizeof(GadiDesc*), ts, sizeof(ts));
-  hipError_t e = hipMemsetAsync(h->ws, 0, l.total, h->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(GadiDesc), hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(tb, tbuf.data(), tbuf.size(), hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return cleanup(fail(GADI_ERR_HIP, std::string("workspace init: ") + hipGetErrorString(e)));
-  if (p->normA > 0.0) {
-    h->normA = p->normA;
-    e = launch_set_norm(h->d_ctl, p->normA, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return cleanup(fail(GADI_ERR_HIP, std::string("set norm: ") + hipGetErrorString(e)));
-  } else {
-    // power iteration on A^H A from a checkerboard start (2 steps per iteration)
-    e = launch_set_phase(h->d_ctl, PH_NORM_A, p->norm_iters, 1.0 / std::sqrt((double)l.n), h->stream);
-    if (e != hipSuccess) return cleanup(fail(GADI_ERR_HIP, std::string("set phase: ") + hipGetErrorString(e)));
-    h->steps = 0;
-    s = launch_steps(h, 2 * p->norm_iters);
-    if (s == GADI_OK) s = read_ctl(h);
-    if (s != GADI_OK) return cleanup(s);
-    if (h->h_ctl->phase != PH_IDLE) return cleanup(fail(GADI_ERR_STATE, "norm estimation did not finish"));
-    h->normA = h->h_ctl->normA;
-  }
+  s = setup_handle(h, st, p, static_cast<hipStream_t>(hip_stream), static_cast<char*>(d_workspace), ws_bytes, l,
+                   nullptr);
+  if (s != GADI_OK) return cleanup(s);
   *out = h;
   return GADI_OK;
 }
