@@ -301,7 +301,9 @@ gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps);
 
 /* Synchronize and report which members are finished: done[i] = 1 for slot i
  * if finished (length max_systems, nullable).  Returns the number of active
- * (unfinished) members through *active. */
+ * (unfinished) members through *active.  One small kernel gathers every
+ * member's control block and one copy brings them to the host, after the
+ * work already enqueued on the batch's stream. */
 gadi_status gadi_batch_poll(gadi_batch* b, int32_t* done, int32_t* active);
 
 /* Report of a finished member, then remove it from the batch. */

@@ -104,6 +104,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run paper_2512_21164_amd.build.build())")
+    # torch first: its HIP runtime is then the one the library binds to, so tensors and
+    # streams from torch and the library's launches share one runtime in the process
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)

@@ -27,6 +27,11 @@
 
 using namespace gadi;
 
+namespace gadi {
+// Copy the control block of each slot (src[i], null: none) to dst[i] (gadi_batch.hip).
+hipError_t launch_gather_ctl(const GadiCtl* const* src, GadiCtl* dst, int n, hipStream_t st);
+}  // namespace gadi
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -936,6 +941,8 @@ struct gadi_batch {
   hipGraphExec_t exec;
   int graph_steps;
   GadiCtl* h_ctls;                    // pinned readback of all members' control blocks
+  GadiCtl** d_ctl_src;                // device: control block of each slot's member (null: none)
+  GadiCtl* d_ctl_dst;                 // device: the gathered control blocks, one per slot
 };
 
 namespace {
@@ -946,6 +953,13 @@ constexpr int kGroupGrid = 2048;     // persistent grid of a batch step launch (
 size_t group_bytes(int max_sys) {
   return align_up(sizeof(BatchTable)) + align_up(sizeof(GadiDesc*) * (size_t)max_sys) +
          align_up(sizeof(int32_t) * (size_t)(max_sys + 1));
+}
+
+// Batch workspace: the class tables, then the slot -> control block pointers
+// and the gathered control blocks of a poll.
+size_t batch_bytes(int max_sys) {
+  return kMaxGroups * group_bytes(max_sys) + align_up(sizeof(GadiCtl*) * (size_t)max_sys) +
+         align_up(sizeof(GadiCtl) * (size_t)max_sys);
 }
 
 gadi_status rebuild_tables(gadi_batch* b) {
@@ -1002,6 +1016,12 @@ gadi_status rebuild_tables(gadi_batch* b) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   }
+  // slot -> control block of an unfinished member, for the gather of a poll
+  std::vector<GadiCtl*> src(b->max_sys, nullptr);
+  for (int i = 0; i < b->max_sys; ++i)
+    if (b->member[i] && !b->done[i]) src[i] = b->member[i]->d_ctl;
+  HIP_TRY(hipMemcpyAsync(b->d_ctl_src, src.data(), src.size() * sizeof(GadiCtl*), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
   b->groups = groups;
   b->dirty = false;
   return GADI_OK;
@@ -1022,7 +1042,7 @@ extern "C" {
 
 gadi_status gadi_batch_workspace_bytes(int32_t max_systems, size_t* bytes) {
   if (!bytes || max_systems < 1) return fail(GADI_ERR_INVALID_ARG, "bad arguments");
-  *bytes = kMaxGroups * group_bytes(max_systems);
+  *bytes = batch_bytes(max_systems);
   return GADI_OK;
 }
 
@@ -1030,7 +1050,7 @@ gadi_status gadi_batch_create(int32_t max_systems, void* hip_stream, void* d_wor
                               gadi_batch** out) {
   if (!out || max_systems < 1) return fail(GADI_ERR_INVALID_ARG, "bad arguments");
   *out = nullptr;
-  size_t need = kMaxGroups * group_bytes(max_systems);
+  size_t need = batch_bytes(max_systems);
   if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return fail(GADI_ERR_WORKSPACE, "bad workspace");
   if (ws_bytes < need) return fail(GADI_ERR_WORKSPACE, "batch workspace too small");
   gadi_batch* b = new gadi_batch();
@@ -1044,6 +1064,9 @@ gadi_status gadi_batch_create(int32_t max_systems, void* hip_stream, void* d_wor
   b->graph = nullptr;
   b->exec = nullptr;
   b->graph_steps = 0;
+  b->d_ctl_src = reinterpret_cast<GadiCtl**>(b->ws + kMaxGroups * group_bytes(max_systems));
+  b->d_ctl_dst = reinterpret_cast<GadiCtl*>(b->ws + kMaxGroups * group_bytes(max_systems) +
+                                            align_up(sizeof(GadiCtl*) * (size_t)max_systems));
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_ctls), sizeof(GadiCtl) * (size_t)max_systems,
                     hipHostMallocDefault) != hipSuccess) {
     delete b;
@@ -1115,11 +1138,15 @@ gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps) {
 
 gadi_status gadi_batch_poll(gadi_batch* b, int32_t* done, int32_t* active) {
   if (!b) return fail(GADI_ERR_INVALID_ARG, "null batch");
-  for (int i = 0; i < b->max_sys; ++i) {
-    gadi_handle* h = b->member[i];
-    if (!h || b->done[i]) continue;
-    HIP_TRY(hipMemcpyAsync(&b->h_ctls[i], h->d_ctl, sizeof(GadiCtl), hipMemcpyDeviceToHost, b->stream));
+  if (b->dirty) {
+    // membership changed since the last step: the gather must see the current members only
+    gadi_status s = rebuild_tables(b);
+    if (s != GADI_OK) return s;
   }
+  // every member's control block in one gather kernel and one copy
+  HIP_TRY(launch_gather_ctl(b->d_ctl_src, b->d_ctl_dst, b->max_sys, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->h_ctls, b->d_ctl_dst, sizeof(GadiCtl) * (size_t)b->max_sys, hipMemcpyDeviceToHost,
+                         b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   int act = 0;
   bool changed = false;

@@ -3,10 +3,11 @@
 Requests (a convection-diffusion system each) arrive over time.  The loop
 admits a waiting request when a batch slot is free and its HBM footprint
 (workspace + b + x) fits in the remaining budget, creates its solver on a
-side stream (so the norm estimate and right-hand side overlap the running
-batch), and adds it to the batch, whose members keep their Krylov state
-resident until they finish.  Between step launches finished members are
-retired and their memory is released.  The loop reports per-request latency
+side stream while the batch stream runs the step enqueued just before (so
+the norm estimate and right-hand side overlap the running batch), and adds it
+to the batch, whose members keep their Krylov state resident until they
+finish.  After each step the batch is polled (one gather of all members'
+control blocks), finished members are retired and their memory is released.  The loop reports per-request latency
 (arrival to result), p50 / p99, and solves per second over the makespan.
 
 Each request carries its own alpha; with ``alpha_source="gpr"`` the server
@@ -57,7 +58,8 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, u_s: str = "f64", tol: float = 1e-10,
                  max_outer: int = 20000, norm_iters: int = 30, steps_per_launch: int = 16, device="cuda",
-                 keep_solutions: bool = False, alpha_source: str = "request", stall_timeout_s=None):
+                 keep_solutions: bool = False, alpha_source: str = "request", stall_timeout_s=None,
+                 autotune: bool = False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -81,6 +83,10 @@ class Server:
         # failure detection: with requests on the device, at least one must finish
         # within this many seconds, else run() raises (None: no limit)
         self.stall_timeout_s = stall_timeout_s
+        # tile shapes: with autotune, the first request of each kernel and size class has the
+        # library time the candidate shapes (once per class and process); every later handle of
+        # the class uses the choice
+        self.autotune = bool(autotune)
 
     def alpha(self, req) -> float:
         """The request's alpha, or the model's prediction for its problem."""
@@ -104,12 +110,18 @@ class Server:
             xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).to(self.device, non_blocking=False)
             b = apply(pr, xt, stream=self.side)
             x = torch.zeros_like(b)
-            s = Solver(pr, stream=self.side, device=self.device, alpha=self.alpha(req), **self.params)
+            s = Solver(pr, stream=self.side, device=self.device, alpha=self.alpha(req), autotune=self.autotune,
+                       **self.params)
         self.side.synchronize()
         return s, b, x, xt
 
     def run(self, trace, time_scale: float = 1.0, log=None) -> List[Result]:
-        """Serve the requests of ``trace`` (arrival times scaled by time_scale)."""
+        """Serve the requests of ``trace`` (arrival times scaled by time_scale).
+
+        Each round enqueues the next batch step first, then prepares newly admitted
+        requests (right-hand side, solver set-up and norm estimate) on the side stream
+        while the device runs that step, then polls the batch, retires finished members
+        and adds the prepared requests."""
         torch = self.torch
         pending = collections.deque(sorted(trace, key=lambda r: r.arrival_s))
         waiting = collections.deque()
@@ -123,7 +135,11 @@ class Server:
             t = now()
             while pending and pending[0].arrival_s * time_scale <= t:
                 waiting.append(pending.popleft())
-            while waiting and len(active) < self.max_slots:
+            stepped = bool(active)
+            if stepped:
+                self.batch.step(self.U)          # asynchronous: the device runs it during admission
+            prepared = []
+            while waiting and len(active) + len(prepared) < self.max_slots:
                 req = waiting[0]
                 fp = self.footprint(req)
                 if fp > self.budget:
@@ -134,14 +150,12 @@ class Server:
                 if used + fp > self.budget:
                     break
                 waiting.popleft()
+                t_adm = now()
                 s, b, x, xt = self._start(req)
-                slot = self.batch.add(s, b, x)
-                last_progress = now()
+                prepared.append((req, t_adm, fp, s, b, x, xt))
                 used += fp
                 self.max_used = max(self.max_used, used)
-                active[slot] = (req, now(), fp, xt)
-            if active:
-                self.batch.step(self.U)
+            if stepped:
                 done, _ = self.batch.poll()
                 for slot in done:
                     s, b, x, rep = self.batch.remove(slot)
@@ -157,11 +171,15 @@ class Server:
                     last_progress = now()
                     if log:
                         log(results[-1])
-                if active and self.stall_timeout_s is not None and now() - last_progress > self.stall_timeout_s:
-                    stuck = sorted(req.rid for req, _, _, _ in active.values())
-                    raise RuntimeError(f"serving stalled: no request finished or was admitted for "
-                                       f"{now() - last_progress:.1f} s; active requests {stuck}")
-            elif pending:
+            for req, t_adm, fp, s, b, x, xt in prepared:
+                slot = self.batch.add(s, b, x)
+                active[slot] = (req, t_adm, fp, xt)
+                last_progress = now()
+            if active and self.stall_timeout_s is not None and now() - last_progress > self.stall_timeout_s:
+                stuck = sorted(req.rid for req, _, _, _ in active.values())
+                raise RuntimeError(f"serving stalled: no request finished or was admitted for "
+                                   f"{now() - last_progress:.1f} s; active requests {stuck}")
+            if not active and not prepared and pending:
                 time.sleep(max(0.0, min(0.002, pending[0].arrival_s * time_scale - now())))
         return results
 
@@ -214,6 +232,7 @@ def main(argv=None):
     ap.add_argument("--us", default="bf16,f64", help="comma-separated inner precisions to run, in order")
     ap.add_argument("--alpha", default="request", choices=["request", "gpr"],
                     help="alpha of each solve: the request's, or the packaged model's prediction")
+    ap.add_argument("--autotune", action="store_true", help="tune the tile shape of each request class on first use")
     ap.add_argument("--stall-timeout", type=float, default=600.0,
                     help="raise if no request finishes or is admitted for this many seconds (0: off)")
     args = ap.parse_args(argv)
@@ -223,7 +242,7 @@ def main(argv=None):
     for us in args.us.split(","):
         srv = Server(int(args.budget_gb * 2 ** 30), max_slots=args.slots, u_s=us, max_outer=args.max_outer,
                      steps_per_launch=args.steps_per_launch, alpha_source=args.alpha,
-                     stall_timeout_s=args.stall_timeout if args.stall_timeout > 0 else None)
+                     stall_timeout_s=args.stall_timeout if args.stall_timeout > 0 else None, autotune=args.autotune)
         done = [0]
 
         def log(r, us=us):
@@ -239,7 +258,7 @@ def main(argv=None):
         srv.close()
     print(json.dumps({"serving": out, "requests": args.requests, "rate_per_s": args.rate,
                       "max_side2d": args.max_side2d, "max_side3d": args.max_side3d, "max_outer": args.max_outer,
-                      "alpha": args.alpha}))
+                      "alpha": args.alpha, "autotune": args.autotune}))
 
 
 if __name__ == "__main__":
