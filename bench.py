@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--us", default="f32", choices=["bf16", "f32"], help="inner precision of the mixed solve")
+    ap.add_argument("--us", default="f32", choices=["bf16", "f32", "f64"],
+                    help="inner precision of the timed solve (f64: plain FP64 GADI, for profiles)")
     ap.add_argument("--u-r", default="f64", choices=["f64", "f64x2"],
                     help="residual precision u_r: FP64, or FP64 pairs (extra precision) for both solves")
     ap.add_argument("--beta", type=float, default=None)
@@ -173,11 +174,13 @@ def traffic_record(workload, us, alpha, beta, inner_tol, u_r="f64", tiling=None)
 
 def hbm_calibration(dev):
     """Plain streaming rates on this GPU (torch kernels, 4 GiB buffers, far beyond the 256 MB
-    Infinity Cache): a read-only reduction, a write-only fill and a copy; best of 5 each, GB/s."""
+    Infinity Cache): a read-only reduction, a write-only fill, a copy and an add (two reads, one
+    write: the read / write mix of the inner passes); best of 5 each, GB/s."""
     import torch
     nbytes = 1 << 32
     a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
+    c = torch.empty_like(a)
     a.fill_(1.0)
     b.fill_(0.0)
     torch.cuda.synchronize()
@@ -194,9 +197,10 @@ def hbm_calibration(dev):
         return out
 
     res = {"read_GBs": best(lambda: a.sum(), nbytes), "write_GBs": best(lambda: b.fill_(2.0), nbytes),
-           "copy_GBs": best(lambda: b.copy_(a), 2 * nbytes), "buffer_bytes": nbytes,
-           "kernels": "torch sum (read), fill_ (write), copy_ (read + write)"}
-    del a, b
+           "copy_GBs": best(lambda: b.copy_(a), 2 * nbytes),
+           "add_GBs": best(lambda: torch.add(a, b, out=c), 3 * nbytes), "buffer_bytes": nbytes,
+           "kernels": "torch sum (read), fill_ (write), copy_ (read + write), add (2 reads + write)"}
+    del a, b, c
     torch.cuda.empty_cache()
     return res
 
@@ -256,7 +260,7 @@ def main():
         alpha = alpha0
     elif args.alpha is None or args.alpha == "gpr":
         from paper_2512_21164_amd.alpha_gpr import predict_alpha
-        alpha = predict_alpha(pr, args.us)
+        alpha = predict_alpha(pr, "f32" if args.us == "f64" else args.us)   # the model knows FP32 and BF16
         alpha_source = "gpr"
     else:
         alpha = float(args.alpha)
@@ -342,7 +346,7 @@ def main():
                        "alg_bytes_per_solve": alg_bytes_unit(r64["outer"], r64["inner_h"], r64["inner_s"], n, 8),
                        "alg_bytes_design_per_solve": alg_bytes(h64, n, 8)}
         out["speedup_mixed_vs_fp64"] = value / out["fp64"]["solves_per_s"]
-    tname = {"bf16": "gadi::bf16", "f32": "float"}[args.us]
+    tname = {"bf16": "gadi::bf16", "f32": "float", "f64": "double"}[args.us]
     kname = f"gadi::gadi_step<{tname}, {dim}, {ry}, {'true' if args.u_r == 'f64x2' else 'false'}>"
     if any(r["restarts"] > 0 for r, _ in reps):
         # the sweep history holds the last attempt only: the bytes of a restarted solve are not known
