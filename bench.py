@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--normA", type=float, default=0.0, help="||A||_2 to use (0: estimate on the device)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64-inner solves (0: skip)")
     ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed FP64-inner solves before the timed ones")
+    ap.add_argument("--bf16-steps", type=int, default=1,
+                    help="timed solves with BF16-stored inner vectors beside the FP32 ones (0: skip)")
+    ap.add_argument("--bf16-warmup", type=int, default=1)
     ap.add_argument("--tile-ry", type=int, default=0, help="3D rows per wave (0: library default)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate tile shapes first (gadi_autotune) and solve with the fastest")
@@ -91,15 +94,21 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes(hist, n, s, w=8, cplx=False):
+def alg_bytes(hist, n, s, w=8, cplx=False, pair_z=None):
     """Bytes this implementation must move in one solve, from its per-sweep iteration counts.
 
     Per unknown (s = bytes of a u_s element, w = bytes of an FP64 element):
     IMPORT 4w; OUTER k=0: 2w+s, k>=1: 3w+3s (3w+2s when the last inner solve
-    took one iteration); CG(H): first pass 2s / 4s / 5s for j = 0 / 1 / >=2,
-    second pass 3s; CGNE(S): start 4s (3s when CG took one iteration), first
-    pass 4s / 5s for j = 1 / >=2, second pass 3s; EXPORT 2w.
+    took one iteration); CG(H) with z updated every second iteration (FP32
+    and FP64 real problems, pair_z): first pass 2s / 3s for j = 0 / odd j,
+    5s / 6s for j = 2 / even j >= 4, and after an even count J the z fold (2s
+    for J = 2, else 3s); without pairing (BF16): first pass 2s / 4s / 5s for
+    j = 0 / 1 / >= 2; second pass 3s;
+    CGNE(S): start 4s (3s when CG took one iteration), first pass 4s / 5s for
+    j = 1 / >=2, second pass 3s; EXPORT 2w.
     """
+    if pair_z is None:
+        pair_z = s >= 4 and (not cplx or s == 8)
     if cplx:
         w, s = 2 * w, 2 * s
     total = 4 * w
@@ -114,7 +123,13 @@ def alg_bytes(hist, n, s, w=8, cplx=False):
             break
         jh, js = int(hist[k][2]), int(hist[k][3])
         for j in range(jh):
-            total += (2 * s if j == 0 else 4 * s if j == 1 else 5 * s) + 3 * s
+            if pair_z:
+                first = 2 * s if j == 0 else (3 * s if j % 2 else (5 * s if j == 2 else 6 * s))
+            else:
+                first = 2 * s if j == 0 else (4 * s if j == 1 else 5 * s)
+            total += first + 3 * s
+        if pair_z and jh >= 2 and jh % 2 == 0:
+            total += 2 * s if jh == 2 else 3 * s
         if not cplx and js > 0:
             total += 4 * s if jh >= 2 else 3 * s
             for j in range(js):
@@ -274,7 +289,7 @@ def main():
     torch.cuda.synchronize()
     nxt = torch.linalg.norm(xt)
 
-    def run(us, steps, warmup):
+    def run(us, steps, warmup, alpha=alpha):
         fixed = {}
         if args.fixed_inner:
             fh, fs = (int(v) for v in args.fixed_inner.split(","))
@@ -346,6 +361,19 @@ def main():
                        "alg_bytes_per_solve": alg_bytes_unit(r64["outer"], r64["inner_h"], r64["inner_s"], n, 8),
                        "alg_bytes_design_per_solve": alg_bytes(h64, n, 8)}
         out["speedup_mixed_vs_fp64"] = value / out["fp64"]["solves_per_s"]
+    if args.bf16_steps > 0 and args.us != "bf16":
+        # the same workload with BF16-stored inner vectors (its own model alpha when alpha is the model's)
+        a16 = alpha
+        if alpha_source == "gpr":
+            from paper_2512_21164_amd.alpha_gpr import predict_alpha
+            a16 = predict_alpha(pr, "bf16")
+        el16, reps16, fe16, _, _ = run("bf16", args.bf16_steps, args.bf16_warmup, alpha=a16)
+        r16, _ = reps16[-1]
+        out["bf16"] = {"solves_per_s": args.bf16_steps / el16, "time_to_solution_s": el16 / args.bf16_steps,
+                       "alpha": a16, "status": r16["status_name"], "outer": r16["outer"], "inner_h": r16["inner_h"],
+                       "inner_s": r16["inner_s"], "be": r16["be"], "forward_error": fe16}
+        if "fp64" in out:
+            out["speedup_bf16_vs_fp64"] = out["bf16"]["solves_per_s"] / out["fp64"]["solves_per_s"]
     tname = {"bf16": "gadi::bf16", "f32": "float", "f64": "double"}[args.us]
     kname = f"gadi::gadi_step<{tname}, {dim}, {ry}, {'true' if args.u_r == 'f64x2' else 'false'}>"
     if any(r["restarts"] > 0 for r, _ in reps):

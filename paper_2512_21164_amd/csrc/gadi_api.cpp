@@ -436,7 +436,7 @@ gadi_status launch_steps(gadi_handle* h, int count) {
 int64_t step_bound(const gadi_params& p, int cplx) {
   const int64_t ih = p.fixed_inner_h > 0 ? p.fixed_inner_h : p.max_inner_h;
   const int64_t is = cplx ? 0 : (p.fixed_inner_s > 0 ? p.fixed_inner_s : p.max_inner_s);
-  const int64_t per = 2 * ih + 2 * is + 2;
+  const int64_t per = 2 * ih + 2 * is + 3;   // + OUTER, the z fold after an even CG count, slack
   return (p.max_outer + 1) * per + 16;
 }
 
@@ -1209,9 +1209,12 @@ void save_tune_entry(const std::string& key, int ry, double factor) {
 }
 
 // Device steps of one sweep in the tuner's fixed-count solve: OUTER, then
-// (H1 H2) per CG iteration, then S0 S2 (S1 S2)^(CGNE iterations - 1).
+// (H1 H2) per CG iteration, the z fold after an even CG count, then
+// S0 S2 (S1 S2)^(CGNE iterations - 1).
 constexpr int kTuneCG = 8, kTuneCGNE = 2;
-int tune_steps_per_sweep(int cplx) { return 1 + 2 * kTuneCG + (cplx ? 0 : 2 * kTuneCGNE); }
+int tune_steps_per_sweep(int us, int cplx) {
+  return 1 + 2 * kTuneCG + (pairs_z(us, cplx) && kTuneCG % 2 == 0 ? 1 : 0) + (cplx ? 0 : 2 * kTuneCGNE);
+}
 
 // Time whole sweeps (every phase, 8 CG and 2 CGNE iterations each) with one
 // tile shape; returns microseconds per sweep.
@@ -1236,7 +1239,7 @@ gadi_status time_shape(const gadi_stencil* st, const gadi_params* base, int ry, 
   gadi_handle* h = nullptr;
   s = gadi_create(st, &q, stream, ws, ws_bytes, &h);
   if (s != GADI_OK) return s;
-  const int per = tune_steps_per_sweep(h->lay.cplx), warm = 1, meas = 2;   // warm + meas < q.max_outer
+  const int per = tune_steps_per_sweep(h->lay.us, h->lay.cplx), warm = 1, meas = 2;   // warm + meas < q.max_outer
   s = start_solve(h, b, x);
   if (s == GADI_OK) s = launch_steps(h, 1 + warm * per);           // IMPORT and a warm-up sweep
   hipEvent_t e0 = h->ec0, e1 = h->ec1;

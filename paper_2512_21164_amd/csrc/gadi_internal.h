@@ -46,10 +46,17 @@ enum Phase : int32_t {
   PH_S1 = 8,       // CGNE(S): p = S^T r + beta p ; lazy y update ; (p, p)
   PH_S2 = 9,       // CGNE(S): r -= a S p ; (r, r)
   PH_EXPORT = 10,  // x^(k) padded -> caller's dense x
-  PH_DONE = 11
+  PH_DONE = 11,
+  PH_ZFOLD = 12    // CG(H) ended after an even number of iterations: z += a_{j-2} p_{j-2}
 };
 
 enum Prec : int32_t { US_F64 = 0, US_F32 = 1, US_BF16 = 2 };
+
+// Inner precisions whose CG updates z every second iteration with two terms
+// (the extra direction loaded for it keeps these kernels at their occupancy;
+// for BF16, complex64 and BF16 pairs it would not, and they update z every
+// iteration).
+__host__ __device__ constexpr bool pairs_z(int us, int cplx) { return us == US_F64 || (us == US_F32 && !cplx); }
 
 struct GadiCtl {
   int32_t phase;
@@ -67,7 +74,8 @@ struct GadiCtl {
   double be, relres, nr0, be_best, be_ref, normb, normA;
   double rho, rho0, a, beta, rho_min, a_prev, aH_last, aS_last;
   double norm_scale;  // 1/||v|| for the power iteration
-  double pad1[3];
+  double a_pair[2];   // CG step size of iteration j in a_pair[j & 1] (z updated every second iteration)
+  double pad1[1];
 };
 
 // Geometry of one tiling: V elements per lane, chunks of L planes along the

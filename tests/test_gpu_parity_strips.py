@@ -90,11 +90,12 @@ def test_lowprec_mirror_3d_multistrip(gpu_lib, prec, ry):
     _mirror_lowprec(spec, b, 12.0, prec, 0.3, 5, 3, 10, tile_ry=ry)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_lowprec_mirror_2d_multistrip(gpu_lib, prec):
-    """2D 1100 x 40: four FP32 strips (256 wide) or two BF16 strips (512 wide) plus a ragged one."""
+@pytest.mark.parametrize("prec,mh", [("f32", 5), ("f32", 4), ("bf16", 5), ("bf16", 4)])
+def test_lowprec_mirror_2d_multistrip(gpu_lib, prec, mh):
+    """2D 1100 x 40: four FP32 strips (256 wide) or two BF16 strips (512 wide) plus a ragged one;
+    an odd and an even CG count (with FP32 the even count ends with the z fold pass)."""
     spec, A, x, b = oracle_system_aniso(2, (1100, 40), (10.0, 10.0), seed=2)
-    _mirror_lowprec(spec, b, 8.0, prec, 0.3, 5, 3, 10)
+    _mirror_lowprec(spec, b, 8.0, prec, 0.3, mh, 3, 10)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])

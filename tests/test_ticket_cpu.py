@@ -1,9 +1,10 @@
 """Two-level completion ticket of the step kernel, modelled on the host.
 
 Every slot of a running system takes one ticket per launch: a ticket of its
-group (slot index mod G, G = min(slots, 16)); the last arrival of a group
-resets the group counter and takes a ticket of the top counter; the arrival
-that completes the top counter finalizes and resets it.  Whatever the arrival
+group (slot index mod G, G = 16); the last arrival of a group resets the group
+counter and takes a ticket of the top counter; the arrival that completes the
+top counter finalizes and resets it.  A system of at most 16 slots takes
+tickets of the top counter directly.  Whatever the arrival
 order, exactly one arrival finalizes, it is the last one, and every counter
 is zero again at the end of the launch.  The last test shows why the count
 has to be the phase-independent slot count: one extra arrival leaves an
@@ -24,9 +25,18 @@ def group_of(tk, ntk):
 
 
 def run_launch(order, ntk, ctr):
-    """Arrivals in the given order; ctr = [top, g0, g1, ...]. Returns the arrival positions that finalize."""
+    """Arrivals in the given order; ctr = [top, g0, g1, ...]. Returns the arrival positions that finalize.
+
+    A system of at most GROUPS slots takes tickets of the top counter directly."""
     fin = []
     for pos, tk in enumerate(order):
+        if ntk <= GROUPS:
+            pt = ctr[0]
+            ctr[0] += 1
+            if pt == ntk - 1:
+                ctr[0] = 0
+                fin.append(pos)
+            continue
         G, g, gsize = group_of(tk, ntk)
         pg = ctr[1 + g]
         ctr[1 + g] += 1
@@ -63,13 +73,19 @@ def test_one_finalize_at_the_last_arrival_and_counters_reset(ntk):
 
 
 def test_an_extra_arrival_stalls_a_later_launch():
-    """One stray arrival in a launch of 17 slots leaves an offset; a later launch of
-    9 slots (single-slot groups) then never finalizes."""
+    """One stray arrival in a launch of 17 slots leaves an offset in a group counter;
+    the slots of a later launch then never complete that group and no launch
+    finalizes.  With at most 16 slots a stray arrival shifts the single counter and
+    the finalize comes one arrival early, before every slot has arrived."""
     ctr = [0] * (1 + GROUPS)
     run_launch([0], 17, ctr)                       # the stray
     assert run_launch(list(range(17)), 17, ctr) != []
     assert ctr != [0] * (1 + GROUPS)
-    assert run_launch(list(range(9)), 9, ctr) == []
+    for _ in range(3):
+        assert run_launch(list(range(17)), 17, ctr) != [16]
+    ctr = [0] * (1 + GROUPS)
+    run_launch([0], 9, ctr)                        # the stray
+    assert run_launch(list(range(9)), 9, ctr) == [7]
 
 
 def _launch_schedule(lim, rng):
