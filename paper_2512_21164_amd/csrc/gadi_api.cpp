@@ -943,11 +943,17 @@ struct gadi_batch {
   GadiCtl* h_ctls;                    // pinned readback of all members' control blocks
   GadiCtl** d_ctl_src;                // device: control block of each slot's member (null: none)
   GadiCtl* d_ctl_dst;                 // device: the gathered control blocks, one per slot
+  // graph branches: class g > 0 is captured on side[g], forked from and joined back into stream
+  hipStream_t side[8];
+  hipEvent_t fork_ev;
+  hipEvent_t join_ev[8];
+  bool branches_ready;
 };
 
 namespace {
 
 constexpr int kMaxGroups = 8;
+static_assert(sizeof(gadi_batch::side) / sizeof(hipStream_t) == kMaxGroups, "one side stream per class");
 constexpr int kGroupGrid = 2048;     // persistent grid of a batch step launch (multiple of 8)
 
 size_t group_bytes(int max_sys) {
@@ -1036,6 +1042,42 @@ gadi_status launch_groups(gadi_batch* b, int nsteps) {
   return GADI_OK;
 }
 
+// Side streams (default priority) and events for the graph branches, created on first use.
+gadi_status ensure_branches(gadi_batch* b) {
+  if (b->branches_ready) return GADI_OK;
+  HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  for (int g = 1; g < kMaxGroups; ++g) {
+    HIP_TRY(hipStreamCreateWithFlags(&b->side[g], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b->join_ev[g], hipEventDisableTiming));
+  }
+  b->branches_ready = true;
+  return GADI_OK;
+}
+
+// The launches of a captured batch step: the classes are independent (each
+// member belongs to one class), so class 0 runs on the batch's stream and
+// every other class on its own side stream, forked from the batch's stream
+// and joined back into it.  The graph then holds one chain of nsteps
+// launches per class, and chains of small members overlap on the device
+// instead of running one after the other.
+gadi_status launch_groups_branched(gadi_batch* b, int nsteps) {
+  const int G = (int)b->groups.size();
+  HIP_TRY(hipEventRecord(b->fork_ev, b->stream));
+  for (int g = 1; g < G; ++g) HIP_TRY(hipStreamWaitEvent(b->side[g], b->fork_ev, 0));
+  for (int s = 0; s < nsteps; ++s)
+    for (int g = 0; g < G; ++g) {
+      const ClassGroup& c = b->groups[g];
+      hipError_t e = launch_step(c.us, c.cplx, c.dim, c.ry, c.xr, StepArgs{c.d_table, c.one, c.one_ctl}, kGroupGrid,
+                                 g == 0 ? b->stream : b->side[g]);
+      if (e != hipSuccess) return fail(GADI_ERR_HIP, std::string("batch step: ") + hipGetErrorString(e));
+    }
+  for (int g = 1; g < G; ++g) {
+    HIP_TRY(hipEventRecord(b->join_ev[g], b->side[g]));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->join_ev[g], 0));
+  }
+  return GADI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1112,8 +1154,12 @@ gadi_status gadi_batch_step(gadi_batch* b, int32_t nsteps) {
     if (!b->exec || b->graph_steps != nsteps) {
       if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
       if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+      if (b->groups.size() > 1) {
+        gadi_status sb = ensure_branches(b);
+        if (sb != GADI_OK) return sb;
+      }
       HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      gadi_status s = launch_groups(b, nsteps);
+      gadi_status s = b->groups.size() > 1 ? launch_groups_branched(b, nsteps) : launch_groups(b, nsteps);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(b->stream, &g);
       if (s != GADI_OK) { if (g) (void)hipGraphDestroy(g); return s; }
@@ -1190,6 +1236,13 @@ gadi_status gadi_batch_destroy(gadi_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->h_ctls) (void)hipHostFree(b->h_ctls);
+  if (b->branches_ready) {
+    (void)hipEventDestroy(b->fork_ev);
+    for (int g = 1; g < kMaxGroups; ++g) {
+      (void)hipStreamDestroy(b->side[g]);
+      (void)hipEventDestroy(b->join_ev[g]);
+    }
+  }
   delete b;
   return GADI_OK;
 }

@@ -38,7 +38,11 @@ def _case(dim, side, beta, alpha, us, seed):
     return s, bd, torch.zeros_like(bd), (A, b, nA)
 
 
-def test_batch_members_equal_solo_runs(gpu_lib):
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_members_equal_solo_runs(gpu_lib, graph):
+    """Five kernel classes in one batch.  On the default stream the steps are launched
+    directly; on a created stream they are captured in a graph with one branch per class."""
+    import torch
     from paper_2512_21164_amd.batch import Batch
     solo = []
     for i, c in enumerate(MIX):
@@ -46,7 +50,8 @@ def test_batch_members_equal_solo_runs(gpu_lib):
         x, rep = s.solve(bd, xd)
         solo.append((x.cpu().numpy(), rep))
         s.close()
-    batch = Batch(16)
+    stream = torch.cuda.Stream() if graph else None
+    batch = Batch(16, stream=stream)
     keep = {}
     for i, c in enumerate(MIX):
         s, bd, xd, sysinfo = _case(*c, seed=i)
