@@ -114,7 +114,10 @@ typedef struct {
                               shape gadi_autotune chose for this class, else the library
                               default (4 for FP64 / FP32 inner solves, 2 for BF16, 1 for
                               complex)                                                    */
-  int32_t tile_chunk;      /* planes per tile along the marching axis; 0: as tile_ry      */
+  int32_t tile_chunk;      /* planes per tile along the marching axis of the inner tiling;
+                              0: as tile_ry; -k (k in 1..64): both tilings' chunks k times
+                              the length that fills the device in one round (k times fewer
+                              tiles, for systems that share the device in a batch)       */
   int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
                               4.3, step 3); 0 (default): none                            */
   double safeguard_tau;    /* > 0: before the solve, raise alpha until

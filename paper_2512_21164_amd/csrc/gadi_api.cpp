@@ -138,7 +138,7 @@ gadi_status validate(const gadi_stencil* st, const gadi_params* p) {
   if (p->normA == 0.0 && p->norm_iters < 1) return fail(GADI_ERR_INVALID_ARG, "norm_iters must be >= 1");
   if (p->tile_ry != 0 && p->tile_ry != 1 && p->tile_ry != 2 && p->tile_ry != 4)
     return fail(GADI_ERR_INVALID_ARG, "tile_ry must be 0, 1, 2 or 4");
-  if (p->tile_chunk < 0 || p->tile_chunk > 4096) return fail(GADI_ERR_INVALID_ARG, "tile_chunk out of range");
+  if (p->tile_chunk < -64 || p->tile_chunk > 4096) return fail(GADI_ERR_INVALID_ARG, "tile_chunk out of range");
   if (!(p->div_factor >= 0.0)) return fail(GADI_ERR_INVALID_ARG, "div_factor must be >= 0");
   if (p->max_restarts < 0 || p->max_restarts > 64) return fail(GADI_ERR_INVALID_ARG, "max_restarts must lie in [0, 64]");
   if (!(p->alpha_growth > 1.0) || !std::isfinite(p->alpha_growth))
@@ -284,7 +284,9 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned 
                         : (l.us == US_F64 ? 2 : (l.us == US_F32 ? 4 : GADI_BF16_V));
   // Chunk length of a tiling: one full round of resident waves (CUs x
   // resident blocks x 4 wave tiles), so that no launch ends with a partial
-  // round.  tile_chunk overrides it for the inner tiling.
+  // round.  tile_chunk > 0 overrides it for the inner tiling; tile_chunk = -k
+  // makes both tilings' chunks k times longer (k times fewer tiles: for a
+  // member of a batch, which shares the device with the other members).
   const int64_t waves = resident_waves(l.us, l.cplx, l.dim, l.RY, l.xr);
   auto one_round = [&](int V) -> int {
     const int64_t nwx = (l.nx + 64 * V - 1) / (64 * V);
@@ -294,10 +296,12 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned 
     return (int)std::max<int64_t>(4, std::min<int64_t>(256, L));
   };
   const int vo = l.cplx ? 1 : 2;
-  l.L = p->tile_chunk > 0 ? p->tile_chunk : one_round(vi);
+  const int share = p->tile_chunk < 0 ? -p->tile_chunk : 1;
+  auto scaled = [&](int L) -> int { return (int)std::min<int64_t>(std::max(l.nm, 1), (int64_t)L * share); };
+  l.L = p->tile_chunk > 0 ? p->tile_chunk : scaled(one_round(vi));
   if (have_tuned)
     l.L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(tuned.chunk_factor * one_round(vi))));
-  l.Lo = one_round(vo);
+  l.Lo = scaled(one_round(vo));
   l.ti = make_tiling(l, vi, l.L);
   l.to = make_tiling(l, vo, l.Lo);
   l.max_tiles = std::max(l.ti.ntiles, l.to.ntiles);

@@ -59,13 +59,19 @@ class Server:
     def __init__(self, budget_bytes: int, max_slots: int = 64, u_s: str = "f64", tol: float = 1e-10,
                  max_outer: int = 20000, norm_iters: int = 30, steps_per_launch: int = 16, device="cuda",
                  keep_solutions: bool = False, alpha_source: str = "request", stall_timeout_s=None,
-                 autotune: bool = False):
+                 autotune: bool = False, client_payload: bool = False, tile_share: int = 4):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.params = dict(u_s=u_s, tol=tol, max_outer=max_outer, norm_iters=norm_iters, omega=1.0)
+        # tile_share k > 1: each request is tiled with k times fewer (longer) tiles than a system
+        # that has the device to itself, since it shares every batch launch with the other members
+        # (every tile of a launch pays a reduction and a ticket; on the serving trace k = 4 served
+        # 27% more FP32 solves per second than k = 1, and k = 2, 6, 8, 16 less than k = 4)
+        if tile_share > 1:
+            self.params["tile_chunk"] = -int(tile_share)
         self.U = int(steps_per_launch)
         self.stream = torch.cuda.Stream(device=self.device)
         self.side = torch.cuda.Stream(device=self.device)
@@ -87,6 +93,13 @@ class Server:
         # library time the candidate shapes (once per class and process); every later handle of
         # the class uses the choice
         self.autotune = bool(autotune)
+        # client_payload: each request brings its right-hand side's data with it (generated, as a client
+        # would, before the trace starts, and kept in pinned host memory); otherwise the loop draws
+        # x_true at admission
+        self.client_payload = bool(client_payload)
+        self._payload: Dict[int, object] = {}
+        # host seconds per part of the loop (admission, step enqueue, poll, retire, add)
+        self.host_s = collections.Counter()
 
     def alpha(self, req) -> float:
         """The request's alpha, or the model's prediction for its problem."""
@@ -107,7 +120,10 @@ class Server:
         torch = self.torch
         pr = request_problem(req)
         with torch.cuda.stream(self.side):
-            xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).to(self.device, non_blocking=False)
+            if req.rid in self._payload:
+                xt = self._payload.pop(req.rid).to(self.device, non_blocking=True)
+            else:
+                xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).to(self.device, non_blocking=False)
             b = apply(pr, xt, stream=self.side)
             x = torch.zeros_like(b)
             s = Solver(pr, stream=self.side, device=self.device, alpha=self.alpha(req), autotune=self.autotune,
@@ -128,6 +144,11 @@ class Server:
         active = {}
         used = 0
         results: List[Result] = []
+        if self.client_payload:
+            import workloads
+            for req in trace:
+                self._payload[req.rid] = torch.from_numpy(workloads.x_true(req.side ** req.dim, req.seed)).pin_memory()
+        hs = self.host_s
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         last_progress = 0.0
@@ -136,8 +157,11 @@ class Server:
             while pending and pending[0].arrival_s * time_scale <= t:
                 waiting.append(pending.popleft())
             stepped = bool(active)
+            tq = time.perf_counter()
             if stepped:
                 self.batch.step(self.U)          # asynchronous: the device runs it during admission
+            ta = time.perf_counter()
+            hs["step"] += ta - tq
             prepared = []
             while waiting and len(active) + len(prepared) < self.max_slots:
                 req = waiting[0]
@@ -151,12 +175,19 @@ class Server:
                     break
                 waiting.popleft()
                 t_adm = now()
+                t1 = time.perf_counter()
                 s, b, x, xt = self._start(req)
+                hs["admit"] += time.perf_counter() - t1
+                hs["admitted"] += 1
                 prepared.append((req, t_adm, fp, s, b, x, xt))
                 used += fp
                 self.max_used = max(self.max_used, used)
             if stepped:
+                tp = time.perf_counter()
                 done, _ = self.batch.poll()
+                tr = time.perf_counter()
+                hs["poll"] += tr - tp
+                hs["rounds"] += 1
                 for slot in done:
                     s, b, x, rep = self.batch.remove(slot)
                     req, t_adm, fp, xt = active.pop(slot)
@@ -171,10 +202,13 @@ class Server:
                     last_progress = now()
                     if log:
                         log(results[-1])
+                hs["retire"] += time.perf_counter() - tr
+            tb = time.perf_counter()
             for req, t_adm, fp, s, b, x, xt in prepared:
                 slot = self.batch.add(s, b, x)
                 active[slot] = (req, t_adm, fp, xt)
                 last_progress = now()
+            hs["add"] += time.perf_counter() - tb
             if active and self.stall_timeout_s is not None and now() - last_progress > self.stall_timeout_s:
                 stuck = sorted(req.rid for req, _, _, _ in active.values())
                 raise RuntimeError(f"serving stalled: no request finished or was admitted for "
@@ -233,6 +267,12 @@ def main(argv=None):
     ap.add_argument("--alpha", default="request", choices=["request", "gpr"],
                     help="alpha of each solve: the request's, or the packaged model's prediction")
     ap.add_argument("--autotune", action="store_true", help="tune the tile shape of each request class on first use")
+    ap.add_argument("--tile-share", type=int, default=4,
+                    help="tile each request with k times fewer tiles than a system alone on the device")
+    ap.add_argument("--client-payload", action="store_true",
+                    help="requests bring their data (x_true drawn before the trace starts, pinned host memory)")
+    ap.add_argument("--results", default=None,
+                    help="write one JSON line per request (per precision) to this file")
     ap.add_argument("--stall-timeout", type=float, default=600.0,
                     help="raise if no request finishes or is admitted for this many seconds (0: off)")
     args = ap.parse_args(argv)
@@ -242,7 +282,8 @@ def main(argv=None):
     for us in args.us.split(","):
         srv = Server(int(args.budget_gb * 2 ** 30), max_slots=args.slots, u_s=us, max_outer=args.max_outer,
                      steps_per_launch=args.steps_per_launch, alpha_source=args.alpha,
-                     stall_timeout_s=args.stall_timeout if args.stall_timeout > 0 else None, autotune=args.autotune)
+                     stall_timeout_s=args.stall_timeout if args.stall_timeout > 0 else None, autotune=args.autotune,
+                     client_payload=args.client_payload, tile_share=args.tile_share)
         done = [0]
 
         def log(r, us=us):
@@ -251,14 +292,26 @@ def main(argv=None):
                 print(f"[serve {us}] {done[0]}/{len(trace)} done, last: rid={r.rid} n={r.n} {r.status} "
                       f"outer={r.outer} latency={r.latency_s:.3f}s", file=sys.stderr, flush=True)
         res = srv.run(trace, log=log)
+        if args.results:
+            by_id = {r.rid: r for r in trace}
+            with open(args.results, "a") as fh:
+                for r in res:
+                    q = by_id[r.rid]
+                    fh.write(json.dumps({"u_s": us, "rid": r.rid, "dim": q.dim, "side": q.side, "n": r.n,
+                                         "beta": q.beta, "arrival_s": r.arrival_s, "admitted_s": r.admitted_s,
+                                         "finished_s": r.finished_s, "status": r.status, "outer": r.outer,
+                                         "inner_h": r.inner_h, "inner_s": r.inner_s, "be": r.be,
+                                         "footprint": r.footprint}) + "\n")
         summ = summarize(res)
+        summ["host_s"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in srv.host_s.items()}
         summ["max_admitted_bytes"] = srv.max_used
         summ["budget_bytes"] = srv.budget
         out[us] = summ
         srv.close()
     print(json.dumps({"serving": out, "requests": args.requests, "rate_per_s": args.rate,
                       "max_side2d": args.max_side2d, "max_side3d": args.max_side3d, "max_outer": args.max_outer,
-                      "alpha": args.alpha, "autotune": args.autotune}))
+                      "alpha": args.alpha, "autotune": args.autotune, "client_payload": args.client_payload,
+                      "steps_per_launch": args.steps_per_launch, "tile_share": args.tile_share}))
 
 
 if __name__ == "__main__":

@@ -59,11 +59,21 @@ def test_workspace_size_scales_with_precision():
                                  dict(max_inner_h=0),
                                  dict(tile_ry=3), dict(tol=-1.0), dict(normA=-1.0), dict(max_restarts=-1),
                                  dict(alpha_growth=1.0), dict(u_s="bf16", safeguard_tau=1e-3),
-                                 dict(safeguard_tau=-1.0)])
+                                 dict(safeguard_tau=-1.0), dict(tile_chunk=-65), dict(tile_chunk=4097)])
 def test_argument_errors(bad):
     pr = api.Problem.convection_diffusion(2, 32, 1.0)
     with pytest.raises(_lib.GadiError):
         _ws(pr, **bad)
+
+
+def test_tile_share_means_fewer_tiles():
+    """tile_chunk = -k: chunks k times longer, so fewer tiles and fewer reduction partials in the
+    workspace (the vectors are the same size)."""
+    pr = api.Problem.convection_diffusion(2, 1024, 3.0)
+    base = _ws(pr, u_s="f32")
+    shares = [_ws(pr, u_s="f32", tile_chunk=-k) for k in (2, 8, 64)]
+    assert base >= shares[0] >= shares[1] >= shares[2]
+    assert base > shares[2]
 
 
 def test_extra_precision_residual_is_accepted_and_sized_like_fp64():

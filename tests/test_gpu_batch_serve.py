@@ -139,7 +139,8 @@ def test_serving_loop_budget_and_solo_equality(gpu_lib):
         pr = request_problem(req)
         xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).cuda()
         b = apply(pr, xt)
-        s = Solver(pr, alpha=req.alpha, u_s="bf16", tol=1e-10, max_outer=3000, norm_iters=30)
+        s = Solver(pr, alpha=req.alpha, u_s="bf16", tol=1e-10, max_outer=3000, norm_iters=30,
+                   tile_chunk=srv.params.get("tile_chunk", 0))      # the server's tiling of its members
         x, rep = s.solve(b, torch.zeros_like(b))
         s.close()
         assert rep["status_name"] == r.status
@@ -168,7 +169,8 @@ def test_serving_with_predicted_alpha(gpu_lib):
         assert srv.alpha(req) == a
         xt = torch.from_numpy(workloads.x_true(pr.size, req.seed)).cuda()
         b = apply(pr, xt)
-        s = Solver(pr, alpha=a, u_s="f32", tol=1e-10, max_outer=3000, norm_iters=30)
+        s = Solver(pr, alpha=a, u_s="f32", tol=1e-10, max_outer=3000, norm_iters=30,
+                   tile_chunk=srv.params.get("tile_chunk", 0))
         x, rep = s.solve(b, torch.zeros_like(b))
         s.close()
         assert rep["status_name"] == r.status
