@@ -285,7 +285,11 @@ gadi_status gadi_alpha_gpr_destroy(gadi_alpha_gpr* m);
  * of its own state machine.  Steps are captured once in a hipGraph and
  * relaunched.  Results of a member do not depend on the other members
  * (each system keeps its own reduction order).  Members keep their Krylov
- * state resident in their own workspaces. */
+ * state resident in their own workspaces.  A member shares every launch
+ * with the others, and each of its tiles pays a reduction and a ticket:
+ * members created with tile_chunk = -k (k times fewer, longer tiles; k = 4
+ * for the serving loop) make the batch's launches shorter.  The steps of
+ * different kernel classes are captured as parallel graph branches. */
 
 /* Device workspace of a batch able to hold max_systems members. */
 gadi_status gadi_batch_workspace_bytes(int32_t max_systems, size_t* bytes);

@@ -144,7 +144,7 @@ def test_fp64_3d_mirror_multistrip(gpu_lib, ry):
     nA = gadi_ref.norm2(A)
     ref = gadi_ref.gadi(A, b, 0.4, 1.0, normA=nA, max_outer=12, rule_h=gadi_ref.InnerRule(fixed=4),
                         rule_s=gadi_ref.InnerRule(fixed=2), record_iterates=True, **FIXED)
-    for chunk in (0, 3):
+    for chunk in (0, 3, -4):     # default, a fixed chunk, and the serving loop's four-times-longer chunks
         xg, rep, hist, tiling = _gpu(spec, b, nA, alpha=0.4, omega=1.0, max_outer=12, fixed_inner_h=4,
                                      fixed_inner_s=2, tile_ry=ry, tile_chunk=chunk, **FIXED)
         assert tiling["ry"] == ry
