@@ -52,11 +52,15 @@ enum Phase : int32_t {
 
 enum Prec : int32_t { US_F64 = 0, US_F32 = 1, US_BF16 = 2 };
 
-// Inner precisions whose CG updates z every second iteration with two terms
-// (the extra direction loaded for it keeps these kernels at their occupancy;
-// for BF16, complex64 and BF16 pairs it would not, and they update z every
-// iteration).
-__host__ __device__ constexpr bool pairs_z(int us, int cplx) { return us == US_F64 || (us == US_F32 && !cplx); }
+// Kernel classes whose CG updates z every second iteration with two terms:
+// FP64 and FP32 (real), complex128, and complex64 in 2D.  Measured on full-size
+// fixed-iteration solves: the pairing made 2D complex64 4.7% faster (with one
+// wave per SIMD less), but BF16 3-5% and BF16 pairs 9% slower, so those and
+// 3D complex64 (whose default shape would lose a wave per SIMD) update z every
+// iteration.
+__host__ __device__ constexpr bool pairs_z(int us, int cplx, int dim) {
+  return us == US_F64 || (us == US_F32 && (!cplx || dim == 2));
+}
 
 struct GadiCtl {
   int32_t phase;
