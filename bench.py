@@ -81,6 +81,8 @@ def parse():
                     help="timed solves with BF16-stored inner vectors beside the FP32 ones (0: skip)")
     ap.add_argument("--bf16-warmup", type=int, default=1)
     ap.add_argument("--tile-ry", type=int, default=0, help="3D rows per wave (0: library default)")
+    ap.add_argument("--tile-chunk", type=int, default=0,
+                    help="planes per wave tile of the inner phases (0: library default; -k: k times the default)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate tile shapes first (gadi_autotune) and solve with the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -296,7 +298,7 @@ def main():
             fixed = dict(fixed_inner_h=fh, fixed_inner_s=fs, stag_window=0, div_factor=0.0)
         s = Solver(pr, alpha=alpha, omega=1.0, u_s=us, u_r=args.u_r, tol=args.tol, max_outer=args.max_outer,
                    inner_tol_h=inner_tol, inner_tol_s=inner_tol, max_restarts=args.max_restarts,
-                   tile_ry=args.tile_ry, autotune=args.autotune, normA=args.normA, **fixed)
+                   tile_ry=args.tile_ry, tile_chunk=args.tile_chunk, autotune=args.autotune, normA=args.normA, **fixed)
         tiling = s.tiling
         reps = []
         x = torch.zeros_like(b)
