@@ -112,8 +112,8 @@ typedef struct {
   int32_t norm_iters;      /* power iterations for the estimate (default 100)             */
   int32_t tile_ry;         /* 3D tile rows per wave (1, 2 or 4); 0 (with tile_chunk 0): the
                               shape gadi_autotune chose for this class, else the library
-                              default (4 for FP64 / FP32 inner solves, 2 for BF16, 1 for
-                              complex)                                                    */
+                              default: 4 for FP64 / FP32 inner solves from 2^24 unknowns,
+                              2 for BF16 from 2^26, 1 below those sizes and for complex */
   int32_t tile_chunk;      /* planes per tile along the marching axis of the inner tiling;
                               0: as tile_ry; -k (k in 1..64): both tilings' chunks k times
                               the length that fills the device in one round (k times fewer

@@ -211,12 +211,17 @@ int64_t resident_waves(int us, int cplx, int dim, int ry, int xr) {
   return waves;
 }
 
-// Rows per wave of 3D tiles (512^3, beta 10, solves to BE 1e-10): four rows for
-// FP32 and FP64 inner solves (9% faster than one row), two for BF16 (3%), where
-// more registers per wave cost more than the halo rows they save.
-int default_ry(int us, int cplx) {
+// Rows per wave of 3D tiles, by kernel class and grid size (fixed-iteration
+// sweeps, microseconds per step launch over 32^3 .. 512^3).  Large grids are
+// bandwidth bound and fewer halo rows pay: four rows for FP32 and FP64 from
+// 2^24 unknowns (256^3: FP64 4% faster than one row, 512^3: FP32 9%), two
+// for BF16 from 2^26 (512^3: 8%).  Below that a launch is short and bound by
+// each wave's latency chain: one row per wave runs three waves per SIMD
+// instead of one and is up to 38% faster (64^3 FP32: 8.7 against 14.1 us).
+int default_ry(int us, int cplx, int64_t n) {
   if (cplx) return 1;
-  return us == US_BF16 ? 2 : 4;
+  if (us == US_BF16) return n >= (int64_t(1) << 26) ? 2 : 1;
+  return n >= (int64_t(1) << 24) ? 4 : 1;
 }
 
 // Tile shapes chosen by the autotuner, per kernel class and size class:
@@ -276,7 +281,7 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned 
     l.ny_plane = 1; l.nm = l.ny; l.sy = l.P; l.sm = l.P; l.RY = 1;
   } else {
     l.ny_plane = l.ny; l.nm = l.nz; l.sy = l.P; l.sm = l.P * l.ny;
-    l.RY = p->tile_ry ? p->tile_ry : (have_tuned ? tuned.ry : default_ry(l.us, l.cplx));
+    l.RY = p->tile_ry ? p->tile_ry : (have_tuned ? tuned.ry : default_ry(l.us, l.cplx, l.n));
   }
   l.nwy = (l.dim == 2) ? 1 : (l.ny_plane + l.RY - 1) / l.RY;
   // elements per lane of the inner phases (16-byte lane accesses)

@@ -83,9 +83,9 @@ def _mirror_lowprec(spec, b, nA, prec, alpha, mh, ms, K, **gpu_kw):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("ry", [0, 1])
+@pytest.mark.parametrize("ry", [1, 2, 4])
 def test_lowprec_mirror_3d_multistrip(gpu_lib, prec, ry):
-    """3D 600 x 8 x 6 (two FP32 or BF16 strips plus a ragged one), default and one row per wave."""
+    """3D 600 x 8 x 6 (two FP32 or BF16 strips plus a ragged one), one, two and four rows per wave."""
     spec, A, x, b = oracle_system_aniso(3, (600, 8, 6), (10.0, 10.0, 10.0), seed=3)
     _mirror_lowprec(spec, b, 12.0, prec, 0.3, 5, 3, 10, tile_ry=ry)
 
