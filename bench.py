@@ -86,7 +86,10 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate tile shapes first (gadi_autotune) and solve with the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps timed for the CPU baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=0,
+                    help="oracle sweeps timed for the CPU baseline (0: as many as fill --cpu-seconds)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU time the oracle sample is sized for when --cpu-sweeps is 0")
     ap.add_argument("--cpu-grid", type=int, default=0,
                     help="grid side of the oracle's sample (0: the workload's; below the full side the "
                          "time is scaled by the unknown count)")
@@ -222,12 +225,13 @@ def hbm_calibration(dev):
     return res
 
 
-def cpu_baseline(dim, ng, ng_sample, beta, alpha, mh, ms, sweeps, us, gpu_outer, normA):
+def cpu_baseline(dim, ng, ng_sample, beta, alpha, mh, ms, sweeps, us, gpu_outer, normA, seconds=15.0):
     """Oracle (CPU, FP64 / emulated u_s) time per sweep on this workload's operator, extrapolated.
 
-    The oracle runs `sweeps` sweeps with the GPU's mean inner iteration counts on the grid of side
-    ng_sample; below the full side its time per sweep is scaled by the unknown count (the oracle's
-    work per sweep is linear in it)."""
+    The oracle runs `sweeps` sweeps (0: one sweep to size the sample, then as many as take about
+    `seconds`) with the GPU's mean inner iteration counts on the grid of side ng_sample; below the
+    full side its time per sweep is scaled by the unknown count (the oracle's work per sweep is
+    linear in it)."""
     import workloads
     from threadpoolctl import threadpool_limits
     from oracle import gadi_ref, problems
@@ -238,17 +242,21 @@ def cpu_baseline(dim, ng, ng_sample, beta, alpha, mh, ms, sweeps, us, gpu_outer,
         b = A @ xs
         rh = gadi_ref.InnerRule(fixed=max(1, mh))
         rs = gadi_ref.InnerRule(fixed=max(1, ms))
-        t0 = time.perf_counter()
-        gadi_ref.gadi(A, b, alpha, 1.0, normA=normA, max_outer=0, tol=0.0, prec=us, rule_h=rh, rule_s=rs)
-        t1 = time.perf_counter()
-        gadi_ref.gadi(A, b, alpha, 1.0, normA=normA, max_outer=sweeps, tol=0.0, prec=us, rule_h=rh, rule_s=rs,
-                      stag_window=0, div_factor=0.0)
-        t2 = time.perf_counter()
-    per_sweep = max((t2 - t1) - (t1 - t0), 1e-9) / sweeps
+        def run(k):
+            t = time.perf_counter()
+            gadi_ref.gadi(A, b, alpha, 1.0, normA=normA, max_outer=k, tol=0.0, prec=us, rule_h=rh, rule_s=rs,
+                          stag_window=0, div_factor=0.0)
+            return time.perf_counter() - t
+        setup = run(0)                      # the oracle's set-up alone, subtracted below
+        if sweeps <= 0:
+            est = max(run(1) - setup, 1e-3)
+            sweeps = int(max(1, min(500, round(seconds / est))))
+        total = run(sweeps)
+    per_sweep = max(total - setup, 1e-9) / sweeps
     scale = float(ng) ** dim / float(ng_sample) ** dim
     solve_s = per_sweep * scale * gpu_outer
     grid = "x".join([str(ng_sample)] * dim)
-    what = (f"{sweeps} GADI sweep(s) in the NumPy/SciPy oracle on the {grid} grid of this operator "
+    what = (f"{sweeps} GADI sweep(s) ({per_sweep * sweeps:.1f} s) in the NumPy/SciPy oracle on the {grid} grid of this operator "
             f"(u_s={us} emulated, CG {mh} + CGNE {ms} iterations per sweep = the GPU's mean), "
             f"{per_sweep:.2f} s/sweep single-threaded")
     if scale != 1.0:
@@ -405,7 +413,7 @@ def main():
         mh = int(round(rep["inner_h"] / max(1, rep["outer"])))
         ms = int(round(rep["inner_s"] / max(1, rep["outer"])))
         out["cpu_baseline"] = cpu_baseline(dim, ng, args.cpu_grid or ng_cpu, beta, alpha, mh, ms, args.cpu_sweeps,
-                                           args.us, int(rep["outer"]), normA)
+                                           args.us, int(rep["outer"]), normA, args.cpu_seconds)
         if args.u_r != "f64":
             out["cpu_baseline"]["sample"] += "; the oracle forms the residual in FP64 (its exact residual is not timed)"
         print("[bench] CPU oracle baseline done", file=sys.stderr, flush=True)
