@@ -115,8 +115,10 @@ typedef struct {
                               default: 4 for FP64 / FP32 inner solves from 2^24 unknowns,
                               2 for BF16 from 2^26, 1 below those sizes and for complex */
   int32_t tile_chunk;      /* planes per tile along the marching axis of the inner tiling;
-                              0: as tile_ry; -k (k in 1..64): both tilings' chunks k times
-                              the length that fills the device in one round (k times fewer
+                              0: as tile_ry (the library default is the length that fills
+                              the device in one round; 2D BF16 takes twice that while half
+                              the resident waves still get a tile); -k (k in 1..64): both
+                              tilings' chunks k times the one-round length (k times fewer
                               tiles, for systems that share the device in a batch)       */
   int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
                               4.3, step 3); 0 (default): none                            */
