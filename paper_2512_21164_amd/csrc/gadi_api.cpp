@@ -316,7 +316,7 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned 
     if (2 * tiles2 >= waves) l.L = L2;
   }
   if (have_tuned)
-    l.L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(tuned.chunk_factor * one_round(vi))));
+    l.L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(tuned.chunk_factor * scaled(one_round(vi)))));
   l.Lo = scaled(one_round(vo));
   l.ti = make_tiling(l, vi, l.L);
   l.to = make_tiling(l, vo, l.Lo);
@@ -1353,7 +1353,9 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
     if (best_us) *best_us = -1.0;
     return GADI_OK;
   }
-  // candidates: every rows-per-wave value (3D) with the one-round chunk, its half and its double
+  // candidates: every rows-per-wave value (3D) with the library's default chunk, its half and
+  // its double; the choice is kept as a multiple of the one-round chunk (tile_chunk = -1),
+  // which is what make_layout scales a tuned entry by
   const std::vector<int> rys = st->dim == 3 ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
   const double factors[3] = {0.5, 1.0, 2.0};
   double best = 1e300, bfac = 1.0;
@@ -1364,6 +1366,8 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
     q.tile_ry = r;
     q.tile_chunk = 0;
     const int Ldef = make_layout(st, &q, false).L;
+    q.tile_chunk = -1;
+    const int Lround = make_layout(st, &q, false).L;
     for (double f : factors) {
       const int L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(f * Ldef)));
       if (std::find(seen.begin(), seen.end(), std::make_pair(r, L)) != seen.end()) continue;
@@ -1373,7 +1377,7 @@ extern "C" gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* 
       if (s != GADI_OK) return s;
       if (std::getenv("GADI_TUNE_VERBOSE"))
         std::fprintf(stderr, "gadi_autotune %s ry=%d chunk=%d: %.2f us per sweep\n", key.c_str(), r, L, us);
-      if (us < best) { best = us; bry = r; bL = L; bfac = (double)L / (double)Ldef; }
+      if (us < best) { best = us; bry = r; bL = L; bfac = (double)L / (double)Lround; }
     }
   }
   *ry = bry;

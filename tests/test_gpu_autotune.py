@@ -81,3 +81,20 @@ def test_tuned_shape_keeps_fp64_mirror_parity(gpu_lib):
                         rule_s=gadi_ref.InnerRule(fixed=2), tol=0.0, stag_window=0, div_factor=0.0)
     print(f"tuned tiling {tiling}: rel {rel(xg.cpu().numpy(), ref.x):.2e}", flush=True)
     assert rel(xg.cpu().numpy(), ref.x) <= 1e-12
+
+
+def test_tuned_2d_bf16_shape_is_used(gpu_lib):
+    """A 2D BF16 class whose default chunk is twice the one-round chunk: the tuned choice is
+    kept relative to the one-round chunk and comes back exactly on handles of the class."""
+    from paper_2512_21164_amd import Problem, Solver, autotune_class
+    pr = Problem.convection_diffusion(2, (8192, 4096), 10.0)
+    kw = dict(alpha=0.01, u_s="bf16", normA=8.0)
+    s = Solver(pr, tile_chunk=-1, **kw)
+    one_round = s.tiling["chunk_inner"]
+    s.close()
+    ry, chunk, us = autotune_class(pr, **kw)
+    assert ry == 1 and us > 0
+    assert chunk in {max(2, round(f * 2 * one_round)) for f in (0.5, 1.0, 2.0)}
+    s = Solver(pr, **kw)
+    assert s.tiling["chunk_inner"] == chunk
+    s.close()
