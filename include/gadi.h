@@ -118,7 +118,8 @@ typedef struct {
                               0: as tile_ry (the library default is the length that fills
                               the device in one round; 2D BF16 takes twice that while half
                               the resident waves still get a tile); -k (k in 1..64): both
-                              tilings' chunks k times the one-round length (k times fewer
+                              tilings' chunks k times the one-round length, or the inner
+                              one k times the tuned chunk of the class (k times fewer
                               tiles, for systems that share the device in a batch)       */
   int32_t max_restarts;    /* alpha restarts on outer stagnation or divergence (Section
                               4.3, step 3); 0 (default): none                            */
@@ -322,8 +323,8 @@ gadi_status gadi_batch_destroy(gadi_batch* b);
 
 /* ---- autotuning -----------------------------------------------------------
  * Choose the tile shape of the step kernels (rows per wave in 3D: 1, 2 or 4;
- * planes per chunk of the inner tiling: half, once or twice the length that
- * fills the device in one round) for this stencil's kernel class (dimension,
+ * planes per chunk of the inner tiling: half, once or twice the library's
+ * default length) for this stencil's kernel class (dimension,
  * real / complex, u_s, u_r) and size class (floor(log2 n)) by timing each
  * candidate on the device: a handle is created in the caller's workspace
  * (ws_bytes must cover the largest candidate layout; gadi_workspace_bytes with
@@ -336,8 +337,9 @@ gadi_status gadi_batch_destroy(gadi_batch* b);
  * appended to it and read back by later processes; a class that already has
  * a choice is not timed again (*best_us = -1).  Every handle created
  * afterwards with tile_ry = tile_chunk = 0 (gadi_create, batches, the
- * allocation-free solve) runs with the shape chosen for its class; create
- * workspaces after tuning, since the shape changes the layout. */
+ * allocation-free solve) runs with the shape chosen for its class, and one
+ * with tile_ry = 0 and tile_chunk = -k with its rows per wave and k times its
+ * chunk; create workspaces after tuning, since the shape changes the layout. */
 gadi_status gadi_autotune(const gadi_stencil* st, const gadi_params* p, void* hip_stream,
                           void* d_workspace, size_t ws_bytes, const void* d_b, void* d_x,
                           int32_t* ry, int32_t* chunk, double* best_us);

@@ -118,11 +118,11 @@ class Solver:
     def __init__(self, problem: Problem, stream=None, device="cuda", workspace=None, autotune: bool = False,
                  **params):
         """autotune: before sizing the workspace, let the library time the tile shapes of this
-        problem's class (once per class and process, see ``autotune``) unless tile_ry or
-        tile_chunk is given."""
+        problem's class (once per class and process, see ``autotune``) unless tile_ry or a
+        positive tile_chunk is given (tile_chunk = -k takes the tuned chunk k times longer)."""
         import torch
         self.lib = _lib.load()
-        if autotune and not params.get("tile_ry") and not params.get("tile_chunk"):
+        if autotune and not params.get("tile_ry") and (params.get("tile_chunk") or 0) <= 0:
             autotune_class(problem, stream=stream, device=device, **params)
         self.problem = problem
         self.params = make_params(**params)

@@ -267,9 +267,10 @@ bool tuned_shape(const gadi_stencil* st, const gadi_params* p, TunedShape* out) 
 }
 
 // use_tuned: consult the autotuner's cache when p leaves the tile shape to the library
+// (tile_ry 0 and tile_chunk 0, or tile_chunk -k: the tuned chunk k times longer)
 Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned = true) {
   TunedShape tuned{0, 0.0};
-  const bool have_tuned = use_tuned && p->tile_ry == 0 && p->tile_chunk == 0 && tuned_shape(st, p, &tuned);
+  const bool have_tuned = use_tuned && p->tile_ry == 0 && p->tile_chunk <= 0 && tuned_shape(st, p, &tuned);
   Layout l{};
   l.dim = st->dim; l.cplx = st->is_complex ? 1 : 0; l.us = p->u_s;
   l.xr = p->u_r == GADI_F64X2 ? 1 : 0;
@@ -315,8 +316,11 @@ Layout make_layout(const gadi_stencil* st, const gadi_params* p, bool use_tuned 
     const int64_t tiles2 = nwx * ((l.nm + L2 - 1) / L2);
     if (2 * tiles2 >= waves) l.L = L2;
   }
-  if (have_tuned)
-    l.L = (int)std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(tuned.chunk_factor * scaled(one_round(vi)))));
+  if (have_tuned) {
+    const int64_t base = std::min<int64_t>(std::max(l.nm, 1), one_round(vi));
+    const int64_t L1 = std::max<int64_t>(2, std::min<int64_t>(4096, std::llround(tuned.chunk_factor * base)));
+    l.L = share == 1 ? (int)L1 : (int)std::min<int64_t>(std::max(l.nm, 1), L1 * share);
+  }
   l.Lo = scaled(one_round(vo));
   l.ti = make_tiling(l, vi, l.L);
   l.to = make_tiling(l, vo, l.Lo);

@@ -98,3 +98,7 @@ def test_tuned_2d_bf16_shape_is_used(gpu_lib):
     s = Solver(pr, **kw)
     assert s.tiling["chunk_inner"] == chunk
     s.close()
+    # a batch member's share (tile_chunk = -k) takes the tuned chunk k times longer
+    s = Solver(pr, tile_chunk=-2, **kw)
+    assert s.tiling["chunk_inner"] == min(4096, 2 * chunk)
+    s.close()
