@@ -99,21 +99,22 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes(hist, n, s, w=8, cplx=False, pair_z=None, dim=3):
+def alg_bytes(hist, n, s, w=8, cplx=False, pair_z=None, dim=3, ry=1):
     """Bytes this implementation must move in one solve, from its per-sweep iteration counts.
 
     Per unknown (s = bytes of a u_s element, w = bytes of an FP64 element):
     IMPORT 4w; OUTER k=0: 2w+s, k>=1: 3w+3s (3w+2s when the last inner solve
     took one iteration); CG(H) with z updated every second iteration (FP32
-    and FP64 real problems, complex128, complex64 in 2D: pair_z): first pass 2s / 3s for j = 0 / odd j,
+    and FP64 real problems, complex128, complex64 in 2D, real BF16 in 3D with ry >= 2 rows per
+    wave: pair_z): first pass 2s / 3s for j = 0 / odd j,
     5s / 6s for j = 2 / even j >= 4, and after an even count J the z fold (2s
-    for J = 2, else 3s); without pairing (BF16): first pass 2s / 4s / 5s for
+    for J = 2, else 3s); without pairing: first pass 2s / 4s / 5s for
     j = 0 / 1 / >= 2; second pass 3s;
     CGNE(S): start 4s (3s when CG took one iteration), first pass 4s / 5s for
     j = 1 / >=2, second pass 3s; EXPORT 2w.
     """
     if pair_z is None:
-        pair_z = s >= 4 and (not cplx or s == 8 or dim == 2)
+        pair_z = (s >= 4 and (not cplx or s == 8 or dim == 2)) or (s == 2 and not cplx and dim == 3 and ry >= 2)
     if cplx:
         w, s = 2 * w, 2 * s
     total = 4 * w
@@ -335,7 +336,7 @@ def main():
     rep, hist = reps[-1]
     value = args.steps / el
     s_b = SBYTES[args.us]
-    bytes_design = alg_bytes(hist, n, s_b)
+    bytes_design = alg_bytes(hist, n, s_b, dim=dim, ry=tiling["ry"])
     bytes_unit = alg_bytes_unit(rep["outer"], rep["inner_h"], rep["inner_s"], n, s_b)
     kern_ms = float(np.mean([r["kernel_ms"] for r, _ in reps]))
     launches = float(np.mean([r["steps"] for r, _ in reps]))

@@ -1289,8 +1289,8 @@ void save_tune_entry(const std::string& key, int ry, double factor) {
 // (H1 H2) per CG iteration, the z fold after an even CG count, then
 // S0 S2 (S1 S2)^(CGNE iterations - 1).
 constexpr int kTuneCG = 8, kTuneCGNE = 2;
-int tune_steps_per_sweep(int us, int cplx, int dim) {
-  return 1 + 2 * kTuneCG + (pairs_z(us, cplx, dim) && kTuneCG % 2 == 0 ? 1 : 0) + (cplx ? 0 : 2 * kTuneCGNE);
+int tune_steps_per_sweep(int us, int cplx, int dim, int ry) {
+  return 1 + 2 * kTuneCG + (pairs_z(us, cplx, dim, ry) && kTuneCG % 2 == 0 ? 1 : 0) + (cplx ? 0 : 2 * kTuneCGNE);
 }
 
 // Time whole sweeps (every phase, 8 CG and 2 CGNE iterations each) with one
@@ -1316,7 +1316,7 @@ gadi_status time_shape(const gadi_stencil* st, const gadi_params* base, int ry, 
   gadi_handle* h = nullptr;
   s = gadi_create(st, &q, stream, ws, ws_bytes, &h);
   if (s != GADI_OK) return s;
-  const int per = tune_steps_per_sweep(h->lay.us, h->lay.cplx, h->lay.dim), warm = 1, meas = 2;   // warm + meas < q.max_outer
+  const int per = tune_steps_per_sweep(h->lay.us, h->lay.cplx, h->lay.dim, h->lay.RY), warm = 1, meas = 2;   // warm + meas < q.max_outer
   s = start_solve(h, b, x);
   if (s == GADI_OK) s = launch_steps(h, 1 + warm * per);           // IMPORT and a warm-up sweep
   hipEvent_t e0 = h->ec0, e1 = h->ec1;

@@ -53,13 +53,15 @@ enum Phase : int32_t {
 enum Prec : int32_t { US_F64 = 0, US_F32 = 1, US_BF16 = 2 };
 
 // Kernel classes whose CG updates z every second iteration with two terms:
-// FP64 and FP32 (real), complex128, and complex64 in 2D.  Measured on full-size
-// fixed-iteration solves: the pairing made 2D complex64 4.7% faster (with one
-// wave per SIMD less), but BF16 3-5% and BF16 pairs 9% slower, so those and
-// 3D complex64 (whose default shape would lose a wave per SIMD) update z every
+// FP64 and FP32 (real), complex128, complex64 in 2D, and real BF16 in 3D with
+// two or more rows per wave.  Measured on full-size fixed-iteration solves:
+// the pairing made 2D complex64 4.7% faster (with one wave per SIMD less) and
+// 3D BF16 with two rows 3.2% faster (same occupancy), but 2D BF16 1% and BF16
+// pairs 5% slower (each losing a wave per SIMD), so those, 3D BF16 with one
+// row and 3D complex64 (both would lose a wave per SIMD) update z every
 // iteration.
-__host__ __device__ constexpr bool pairs_z(int us, int cplx, int dim) {
-  return us == US_F64 || (us == US_F32 && (!cplx || dim == 2));
+__host__ __device__ constexpr bool pairs_z(int us, int cplx, int dim, int ry) {
+  return us == US_F64 || (us == US_F32 && (!cplx || dim == 2)) || (us == US_BF16 && !cplx && dim == 3 && ry >= 2);
 }
 
 struct GadiCtl {
