@@ -8,11 +8,10 @@ when every candidate is timed again independently (fixed-count solves, best
 of three), handles pick the choice up, and the FP64 path with the tuned shape
 still matches the oracle to 1e-12 in mirror mode.
 """
-import numpy as np
 import pytest
 
 import workloads
-from oracle import gadi_ref, problems
+from oracle import gadi_ref
 from tests._problems import gpu_problem, oracle_system_aniso, rel, to_dev
 
 pytestmark = pytest.mark.gpu

@@ -122,7 +122,7 @@ def test_batch_add_while_running(gpu_lib):
 
 def test_serving_loop_budget_and_solo_equality(gpu_lib):
     import torch
-    from paper_2512_21164_amd import Problem, Solver, apply
+    from paper_2512_21164_amd import Solver, apply
     from paper_2512_21164_amd.serve import Server, request_problem, summarize
     trace = workloads.scale_trace(workloads.poisson_trace(num=20, rate_per_s=400.0, seed=3), 80, 20)
     trace = [t for t in trace]
