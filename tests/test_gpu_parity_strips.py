@@ -106,8 +106,11 @@ def test_complex_lowprec_mirror_multistrip(gpu_lib, prec):
     _mirror_lowprec(spec, b, 8.0, prec, 0.2, 6, 1, 10)
 
 
-@pytest.mark.parametrize("case", ["2d-1100x40", "3d-600x8x6", "complex-300x12"])
+@pytest.mark.parametrize("case", ["2d-1100x40", "3d-600x8x6", "3d-600x8x6-ry2", "complex-300x12"])
 def test_bf16_multistrip_reaches_1e10(gpu_lib, case):
+    """Mixed BF16 solves to BE 1e-10 recomputed by the oracle; the 3D grid also with two rows per
+    wave, the 3D BF16 shape that updates z every second CG iteration."""
+    kw = dict(tile_ry=2) if case.endswith("ry2") else {}
     if case.startswith("2d"):
         spec, A, x, b = oracle_system_aniso(2, (1100, 40), (10.0, 10.0), seed=2)
     elif case.startswith("3d"):
@@ -117,9 +120,10 @@ def test_bf16_multistrip_reaches_1e10(gpu_lib, case):
         A = problems.assemble(spec)
         b = workloads.complex_rhs(spec.size, 8)
     nA = gadi_ref.norm2(A)
-    xg, rep, hist, tiling = _gpu(spec, b, nA, alpha=0.3, omega=1.0, u_s="bf16", tol=1e-10, max_outer=8000)
+    xg, rep, hist, tiling = _gpu(spec, b, nA, alpha=0.3, omega=1.0, u_s="bf16", tol=1e-10, max_outer=8000, **kw)
     be = gadi_ref.backward_error(A, xg, b, nA, extended=True)
     print(f"{case}: {rep['status_name']} sweeps {rep['outer']} BE {be:.3e} {tiling}", flush=True)
+    assert tiling["ry"] == kw.get("tile_ry", tiling["ry"])
     assert rep["status"] == 0
     assert be <= 1.01e-10
 
