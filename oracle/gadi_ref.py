@@ -169,6 +169,13 @@ def cgne(S, c, rule: InnerRule, prec: str = "f64"):
             rho = rho_new
 
 
+def _be(nr, denom):
+    """||r|| / (||A|| ||x|| + ||b||), and 0 for an exact residual: the backward error is the
+    smallest relative perturbation of A and b that x solves exactly (Section 3), which is zero
+    when r = 0, also where the quotient is 0 / 0 (b = 0 and x = 0)."""
+    return 0.0 if nr == 0 else float(nr / denom)
+
+
 def backward_error(A, x, b, normA: float, extended: bool = False) -> float:
     """Normwise backward error ||b - A x|| / (||A|| ||x|| + ||b||), 2-norms (Section 3).
 
@@ -183,9 +190,9 @@ def backward_error(A, x, b, normA: float, extended: bool = False) -> float:
         nr = np.sqrt(np.sum(np.abs(r) ** 2))
         nx = np.sqrt(np.sum(np.abs(xl) ** 2))
         nb = np.sqrt(np.sum(np.abs(bl) ** 2))
-        return float(nr / (np.longdouble(normA) * nx + nb))
+        return _be(nr, np.longdouble(normA) * nx + nb)
     r = b - A @ x
-    return float(np.linalg.norm(r) / (normA * np.linalg.norm(x) + np.linalg.norm(b)))
+    return _be(np.linalg.norm(r), normA * np.linalg.norm(x) + np.linalg.norm(b))
 
 
 def backward_error_stencil(spec, x, b, normA: float) -> float:
@@ -202,7 +209,7 @@ def backward_error_stencil(spec, x, b, normA: float) -> float:
     del r
     nx = np.sqrt(np.sum(np.abs(xl) ** 2))
     nb = np.sqrt(np.sum(np.abs(np.asarray(b).astype(dt)) ** 2))
-    return float(nr / (np.longdouble(normA) * nx + nb))
+    return _be(nr, np.longdouble(normA) * nx + nb)
 
 
 def _split(v):
@@ -331,7 +338,7 @@ def gadi(A, b, alpha: float, omega: float, *, normA: float, tol: float = 1e-10,
                 res.iterates.append(x.copy())
             r = residual(A, b, x, u_r)                       # residual in u_r
             nr = float(np.linalg.norm(r))
-            be = nr / (normA * float(np.linalg.norm(x)) + normb)
+            be = _be(nr, normA * float(np.linalg.norm(x)) + normb)
             if nr0 is None:
                 nr0 = nr
             relres = nr / nr0 if nr0 > 0 else 0.0

@@ -165,6 +165,12 @@ def test_edge_cases(gpu_lib):
     xg, rep, hist = _gpu_solve(spec, b, nA, x0=x0, alpha=0.5, max_outer=0)
     assert rep["status"] == gadi_ref.NOT_CONVERGED and np.array_equal(xg, x0)
     assert abs(hist[0, 0] - gadi_ref.backward_error(A, x0, b, nA)) <= 1e-15
+    # b = 0: the zero start is the exact solution (backward error 0, not 0 / 0), as in the oracle
+    z = np.zeros_like(b)
+    ref = gadi_ref.gadi(A, z, 0.5, 1.0, normA=nA, tol=1e-12, max_outer=10)
+    xg, rep, hist = _gpu_solve(spec, z, nA, alpha=0.5, tol=1e-12, max_outer=10)
+    assert rep["status"] == ref.status == gadi_ref.OK and rep["outer"] == ref.outer == 0
+    assert hist[0, 0] == 0.0 and not np.any(xg)
 
 
 def test_status_codes(gpu_lib):

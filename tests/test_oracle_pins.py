@@ -201,6 +201,28 @@ def test_backward_error_is_realised_by_a_perturbation():
     assert abs(gadi_ref.backward_error(A, xh, b, nA, extended=True) - eps) <= 1e-12 * eps
 
 
+def test_backward_error_of_an_exact_solution_is_zero():
+    """The backward error is the smallest relative perturbation of A and b that x solves exactly
+    (Section 3); an exact x needs none, so it is 0, also for b = 0 and x = 0 where the quotient
+    of the formula is 0 / 0.  With b = 0 the zero start is that exact solution: GADI stops at
+    sweep 0 with status OK instead of reading 0 / 0 as a non-finite (diverged) backward error."""
+    spec, A, x, b = _small_system(ng=6)
+    nA = gadi_ref.norm2(A)
+    z = np.zeros_like(b)
+    assert gadi_ref.backward_error(A, z, z, nA) == 0.0
+    assert gadi_ref.backward_error(A, z, z, nA, extended=True) == 0.0
+    assert gadi_ref.backward_error_stencil(spec, z, z, nA) == 0.0
+    s0, A0, x0, _ = _small_system(ng=6, beta=(0.0, 0.0))   # integer stencil: -1 and 4
+    xd = np.round(x0 * 8) / 8                               # dyadic, so A0 xd is exact in FP64
+    assert gadi_ref.backward_error(A0, xd, A0 @ xd, gadi_ref.norm2(A0), extended=True) == 0.0
+    res = gadi_ref.gadi(A, z, 0.5, 1.0, normA=nA, tol=1e-12, max_outer=10)
+    assert res.status == gadi_ref.OK and res.outer == 0 and res.be == [0.0]
+    assert not np.any(res.x)
+    # a non-zero start with b = 0 has a finite, positive backward error (x = 0 is the solution)
+    res = gadi_ref.gadi(A, z, 0.5, 1.0, normA=nA, x0=x, tol=0.0, max_outer=0)
+    assert 0.0 < res.be[0] <= 1.0
+
+
 @pytest.mark.parametrize("ng,beta,alpha", [(8, (1.0, 1.0), 0.5), (12, (30.0, 10.0), 0.2),
                                            (16, (5.0, 50.0), 0.1)])
 def test_converged_solution_matches_dense_lu(ng, beta, alpha):
